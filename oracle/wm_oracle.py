@@ -1,0 +1,363 @@
+"""FP64 CPU oracle of the WeatherMesh-3 latent processor step.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or
+calls this module; only the tests, the smoke check and the CPU-baseline leg
+of the benchmark do.  It shares no code with the HIP path: the only common
+dependency is the seeded input generator (``wm_synth``), which holds none of
+the method's arithmetic.
+
+Everything is computed in float64 from the float32 master values, literally
+as the method is defined, with no blocking, fusion or reordering beyond what
+the definitions state.  Library primitives used as steps: ``numpy.matmul``
+(dense products), ``numpy.take`` (gathers), ``scipy.special.erf``.
+
+What is computed (section references are to the WeatherMesh-3 paper):
+
+* Neighborhoods (Sec. 2.1 "NATTEN"; App. A.2 "Model Architecture"): every
+  latent token attends to the Kz x Ky x Kx box of tokens around it over
+  (level, lat, lon).  Longitude wraps (the paper's own circular padding,
+  App. A.2); latitude uses NATTEN's border behaviour, where the window keeps
+  its full size and shifts inward at the poles ("bump attention", App. A.2);
+  the level axis is treated like latitude.
+* Relative-position bias: a learned per-head table indexed by the key minus
+  query offset on each axis.  The paper itself encodes position with rotary
+  embeddings (App. A.2); this build follows the bias formulation.
+* Block: a pre-norm transformer block (the vision-transformer layout the
+  paper builds on, Sec. 2.1) with LayerNorm, QKV projection, neighborhood
+  attention, output projection, residual, LayerNorm, GELU MLP, residual.
+* Processor step: the blocks of one processor applied in order (Sec. 2.1,
+  "Encoder-processor-decoder architecture").
+* Rollout: six-hour steps then one-hour steps chosen by the greedy schedule,
+  all in latent space (Sec. 2.1, latent rollout).
+
+Readings taken where the paper is silent (all listed in the design notes):
+pre-norm, no final norm; LayerNorm eps 1e-5 with biased variance; exact erf
+GELU; biases on all four linear maps; scores scaled by 1/sqrt(d) before the
+bias is added; joint 3-D bias table per head of shape
+[H, 2Kz-1, 2Ky-1, 2Kx-1] indexed by offset + K - 1; greedy schedule takes
+all six-hour steps first.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import numpy as np
+from scipy.special import erf
+
+__all__ = [
+    "window_axis", "neighbor_ids", "neighborhood_attention", "nat_at",
+    "layer_norm", "gelu", "block", "block_at", "processor_step",
+    "schedule", "rollout", "rel_l2", "nat_c", "oracle_threads",
+]
+
+LN_EPS = 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Neighborhood windows (Sec. 2.1 NATTEN; App. A.2 circular padding and bump
+# attention at the poles).
+# ---------------------------------------------------------------------------
+def window_axis(N: int, K: int, periodic: bool):
+    """Window of every position i on one axis of length N, odd K <= N.
+
+    Returns ``keys`` [N, K] (key coordinates, t = 0..K-1 in order) and
+    ``off`` [N, K] (key - query offset delta used to index the bias).
+
+    Periodic axis: keys (i - r + t) mod N, offset t - r (a centered window
+    that wraps around the sphere).
+    Clamped axis: the window keeps its K entries and slides inward at the
+    border: start(i) = min(max(i - r, 0), N - K), keys start + t, offset
+    key - i.
+    """
+    if K % 2 != 1 or K < 1 or K > N:
+        raise ValueError(f"window {K} invalid for axis of length {N}")
+    r = (K - 1) // 2
+    i = np.arange(N, dtype=np.int64)[:, None]
+    t = np.arange(K, dtype=np.int64)[None, :]
+    if periodic:
+        keys = (i - r + t) % N
+        off = np.broadcast_to(t - r, (N, K)).copy()
+    else:
+        start = np.minimum(np.maximum(i - r, 0), N - K)
+        keys = start + t
+        off = keys - i
+    return keys, off
+
+
+def _axes(g):
+    return ((g.Z, g.Kz, bool(g.periodic_mask & 1)),
+            (g.Y, g.Ky, bool(g.periodic_mask & 2)),
+            (g.X, g.Kx, bool(g.periodic_mask & 4)))
+
+
+def neighbor_ids(g, tokens: np.ndarray):
+    """Neighborhood of each query token (flat index (z*Y + y)*X + x).
+
+    Returns key token ids [n, Kz*Ky*Kx], enumerated in (tz, ty, tx) order
+    with tx fastest, and the bias-table indices (iz, iy, ix) [n, Kvol]
+    (offset + K - 1 on each axis).
+    """
+    tokens = np.asarray(tokens, dtype=np.int64)
+    (Z, Kz, pz), (Y, Ky, py), (X, Kx, px) = _axes(g)
+    kz, oz = window_axis(Z, Kz, pz)
+    ky, oy = window_axis(Y, Ky, py)
+    kx, ox = window_axis(X, Kx, px)
+    z = tokens // (Y * X)
+    y = (tokens // X) % Y
+    x = tokens % X
+    n = tokens.shape[0]
+    ids = (kz[z][:, :, None, None] * (Y * X)
+           + ky[y][:, None, :, None] * X
+           + kx[x][:, None, None, :])
+    iz = np.broadcast_to((oz[z] + Kz - 1)[:, :, None, None], ids.shape)
+    iy = np.broadcast_to((oy[y] + Ky - 1)[:, None, :, None], ids.shape)
+    ix = np.broadcast_to((ox[x] + Kx - 1)[:, None, None, :], ids.shape)
+    return (ids.reshape(n, -1), iz.reshape(n, -1), iy.reshape(n, -1),
+            ix.reshape(n, -1))
+
+
+def _attend(qrows, krows, vrows, bias, d):
+    """Softmax attention of n queries over their own Kvol keys.
+
+    qrows [n, H, d]; krows, vrows [n, Kvol, H, d]; bias [n, H, Kvol].
+    s = q.k / sqrt(d) + bias; p = softmax over the Kvol keys (max
+    subtracted); o = sum_k p v.
+    """
+    s = np.einsum("nhd,nkhd->nhk", qrows, krows) / math.sqrt(d) + bias
+    s = s - s.max(axis=-1, keepdims=True)
+    p = np.exp(s)
+    p = p / p.sum(axis=-1, keepdims=True)
+    o = np.einsum("nhk,nkhd->nhd", p, vrows)
+    return o, p
+
+
+def neighborhood_attention(q, k, v, rpb, g, return_probs=False, chunk=256):
+    """3-D neighborhood attention of one latent state.
+
+    q, k, v: [T, H, d] (token-major, T = Z*Y*X); rpb: [H, 2Kz-1, 2Ky-1,
+    2Kx-1].  Returns o [T, H, d] (and probabilities [T, H, Kvol] if asked).
+    """
+    q = np.asarray(q, np.float64)
+    k = np.asarray(k, np.float64)
+    v = np.asarray(v, np.float64)
+    rpb = np.asarray(rpb, np.float64)
+    T, H, d = q.shape
+    o = np.empty_like(q)
+    probs = np.empty((T, H, g.Kz * g.Ky * g.Kx)) if return_probs else None
+    for s0 in range(0, T, chunk):
+        tok = np.arange(s0, min(T, s0 + chunk))
+        ids, iz, iy, ix = neighbor_ids(g, tok)
+        bias = rpb[:, iz, iy, ix].transpose(1, 0, 2)      # [n, H, Kvol]
+        oc, pc = _attend(q[tok], k[ids], v[ids], bias, d)
+        o[tok] = oc
+        if return_probs:
+            probs[tok] = pc
+    return (o, probs) if return_probs else o
+
+
+_CLIB = None
+
+
+def _clib():
+    """The C loop version of the attention (oracle/nat_ref.c), if built."""
+    global _CLIB
+    if _CLIB is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                            "liboracle_nat.so")
+        if not os.path.exists(path):
+            return None
+        lib = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_nat.argtypes = [ctypes.c_int] * 8 + [ctypes.c_uint] + [dp] * 6
+        lib.oracle_nat.restype = ctypes.c_int
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _CLIB = lib
+    return _CLIB
+
+
+def oracle_threads() -> int:
+    lib = _clib()
+    return lib.oracle_num_threads() if lib is not None else 1
+
+
+def nat_c(q, k, v, rpb, g, return_probs=False):
+    """Same attention as ``neighborhood_attention``, as plain C loops.
+
+    Used for full-size grids, where the vectorised gather above is too slow.
+    """
+    lib = _clib()
+    if lib is None:
+        raise RuntimeError("oracle C library not built (oracle/build_oracle.py)")
+    q = np.ascontiguousarray(q, np.float64)
+    k = np.ascontiguousarray(k, np.float64)
+    v = np.ascontiguousarray(v, np.float64)
+    rpb = np.ascontiguousarray(rpb, np.float64)
+    T, H, d = q.shape
+    out = np.empty_like(q)
+    probs = np.empty((T, H, g.Kz * g.Ky * g.Kx)) if return_probs else None
+    dp = ctypes.POINTER(ctypes.c_double)
+    cast = lambda a: a.ctypes.data_as(dp) if a is not None else None
+    rc = lib.oracle_nat(g.Z, g.Y, g.X, H, d, g.Kz, g.Ky, g.Kx,
+                        g.periodic_mask, cast(q), cast(k), cast(v), cast(rpb),
+                        cast(out), cast(probs))
+    if rc != 0:
+        raise ValueError("oracle_nat rejected the grid/window")
+    return (out, probs) if return_probs else out
+
+
+def _nat_any(q, k, v, rpb, g):
+    if _clib() is not None:
+        return nat_c(q, k, v, rpb, g)
+    return neighborhood_attention(q, k, v, rpb, g)
+
+
+# ---------------------------------------------------------------------------
+# Block pieces.
+# ---------------------------------------------------------------------------
+def layer_norm(x, gamma, beta, eps=LN_EPS):
+    """LayerNorm over the channel axis: mean, biased variance (1/C), eps."""
+    x = np.asarray(x, np.float64)
+    mu = x.mean(axis=-1, keepdims=True)
+    var = ((x - mu) ** 2).mean(axis=-1, keepdims=True)
+    return (x - mu) / np.sqrt(var + eps) * np.asarray(gamma, np.float64) \
+        + np.asarray(beta, np.float64)
+
+
+def gelu(z):
+    """GELU with the exact Gaussian CDF: z * Phi(z) = z/2 * (1 + erf(z/sqrt2))."""
+    z = np.asarray(z, np.float64)
+    return 0.5 * z * (1.0 + erf(z / math.sqrt(2.0)))
+
+
+def _p64(p):
+    return {k: np.asarray(v, np.float64) for k, v in p.items()}
+
+
+def _qkv_heads(u, p, g):
+    qkv = u @ p["w_qkv"] + p["b_qkv"]
+    C, H, d = g.C, g.heads, g.d
+    q = qkv[..., 0 * C:1 * C].reshape(*qkv.shape[:-1], H, d)
+    k = qkv[..., 1 * C:2 * C].reshape(*qkv.shape[:-1], H, d)
+    v = qkv[..., 2 * C:3 * C].reshape(*qkv.shape[:-1], H, d)
+    return q, k, v
+
+
+def _mlp_half(x1, p):
+    w = layer_norm(x1, p["ln2_g"], p["ln2_b"])
+    return x1 + gelu(w @ p["w_1"] + p["b_1"]) @ p["w_2"] + p["b_2"]
+
+
+def block(x, p, g):
+    """One pre-norm neighborhood-attention transformer block.
+
+    x: [B, Z, Y, X, C] (or [Z, Y, X, C]); p: dict of one block's parameters
+    (canonical names of ``wm_synth.block_param_layout``).
+      u  = LN1(x)
+      q, k, v = u W_qkv + b_qkv, split into heads (channel = head*d + e)
+      o  = neighborhood attention with relative-position bias
+      x1 = x + o W_o + b_o
+      x2 = x1 + GELU(LN2(x1) W_1 + b_1) W_2 + b_2
+    """
+    p = _p64(p)
+    x = np.asarray(x, np.float64)
+    squeeze = x.ndim == 4
+    if squeeze:
+        x = x[None]
+    B = x.shape[0]
+    out = np.empty_like(x)
+    for b in range(B):
+        xb = x[b].reshape(g.T, g.C)
+        u = layer_norm(xb, p["ln1_g"], p["ln1_b"])
+        q, k, v = _qkv_heads(u, p, g)
+        o = _nat_any(q, k, v, p["rpb"], g).reshape(g.T, g.C)
+        x1 = xb + o @ p["w_o"] + p["b_o"]
+        out[b] = _mlp_half(x1, p).reshape(g.Z, g.Y, g.X, g.C)
+    return out[0] if squeeze else out
+
+
+def nat_at(q, k, v, rpb, g, tokens):
+    """Neighborhood attention output at the given query tokens only.
+
+    q, k, v: [T, H, d]; returns [n, H, d].
+    """
+    tokens = np.asarray(tokens, np.int64)
+    ids, iz, iy, ix = neighbor_ids(g, tokens)
+    rpb = np.asarray(rpb, np.float64)
+    bias = rpb[:, iz, iy, ix].transpose(1, 0, 2)
+    o, _ = _attend(np.asarray(q[tokens], np.float64),
+                   np.asarray(k[ids], np.float64),
+                   np.asarray(v[ids], np.float64), bias, g.d)
+    return o
+
+
+def block_at(x, p, g, tokens):
+    """Block output of one state at the given tokens only.
+
+    x: [Z, Y, X, C] (or [T, C]).  Every token's output depends on its own
+    input and on the keys and values of its neighborhood, so only those
+    tokens go through LN1 and the QKV projection.  Returns [n, C].
+    """
+    p = _p64(p)
+    xf = np.asarray(x).reshape(g.T, g.C)
+    tokens = np.asarray(tokens, np.int64)
+    ids, iz, iy, ix = neighbor_ids(g, tokens)
+    need, inv = np.unique(np.concatenate([tokens, ids.ravel()]),
+                          return_inverse=True)
+    u = layer_norm(np.asarray(xf[need], np.float64), p["ln1_g"], p["ln1_b"])
+    q, k, v = _qkv_heads(u, p, g)
+    n = tokens.shape[0]
+    qi = inv[:n]
+    ki = inv[n:].reshape(ids.shape)
+    bias = p["rpb"][:, iz, iy, ix].transpose(1, 0, 2)
+    o, _ = _attend(q[qi], k[ki], v[ki], bias, g.d)
+    x1 = np.asarray(xf[tokens], np.float64) + o.reshape(n, g.C) @ p["w_o"] + p["b_o"]
+    return _mlp_half(x1, p)
+
+
+def processor_step(x, params_blocks, g):
+    """One processor step: its blocks applied in order (Sec. 2.1)."""
+    for p in params_blocks:
+        x = block(x, p, g)
+    return x
+
+
+# ---------------------------------------------------------------------------
+# Latent rollout (Sec. 2.1, latent rollout with a greedy schedule).
+# ---------------------------------------------------------------------------
+def schedule(lead_hours: int):
+    """Greedy 6 h / 1 h schedule for an integer lead time.
+
+    Largest step first: floor(L/6) six-hour steps, then L mod 6 one-hour
+    steps.  Lead 0 is the identity (no step); a negative lead is an error.
+    """
+    L = int(lead_hours)
+    if L < 0:
+        raise ValueError("negative lead time")
+    steps = []
+    remaining = L
+    for size in (6, 1):
+        while remaining >= size:
+            steps.append(size)
+            remaining -= size
+    return steps
+
+
+def rollout(x, params6, params1, g, lead_hours, on_step=None):
+    """Run the processors on the latent state under the greedy schedule.
+
+    ``on_step(i, size, x)`` is called after every step if given.
+    """
+    x = np.asarray(x, np.float64)
+    for i, s in enumerate(schedule(lead_hours)):
+        x = processor_step(x, params6 if s == 6 else params1, g)
+        if on_step is not None:
+            on_step(i, s, x)
+    return x
+
+
+def rel_l2(y, y_ref):
+    """Relative L2 error ||y - y_ref|| / ||y_ref|| accumulated in float64."""
+    y = np.asarray(y, np.float64).ravel()
+    r = np.asarray(y_ref, np.float64).ravel()
+    return float(np.linalg.norm(y - r) / np.linalg.norm(r))
