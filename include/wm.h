@@ -1,0 +1,188 @@
+/*
+ * wm.h -- C ABI of the MI355X latent processor library (libwm.so).
+ *
+ * WeatherMesh-3 (arXiv 2503.22235) forecasts by encoding the weather state
+ * into a 2-degree latent grid, running a processor (a stack of
+ * neighborhood-attention transformer blocks) on that latent any number of
+ * times -- one call advances one hour or six hours -- and decoding
+ * (Sec. 2.1, "Encoder-processor-decoder architecture").  The problem it
+ * solves is stated there: from a single state, predict the state any integer
+ * number of hours later.  This library is the latent part of that path on
+ * one GPU: the neighborhood attention (wm_nat_forward), one transformer
+ * block (wm_processor_block), one processor step (wm_processor_step), the
+ * greedy rollout (wm_schedule, wm_rollout) and a continuous-batching
+ * request loop (wm_serve_*).
+ *
+ * Conventions shared by every entry point:
+ *  - Grid axes are (Z = pressure level, Y = latitude, X = longitude); a
+ *    state is [B][Z][Y][X][C] float32, channels last, token
+ *    t = (z*Y + y)*X + x.  Channel c of an attention head is h*d + e with
+ *    d = C / heads (d must be 32).
+ *  - Tensor pointers are DEVICE pointers owned by the caller unless a
+ *    comment says host.  The library never frees caller memory.
+ *  - Streams are hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is enqueued on that stream; calls return without waiting for the
+ *    GPU unless stated otherwise.
+ *  - Every int-returning call returns WM_OK (0) or a negative wm_status;
+ *    wm_last_error() then holds a message for the calling thread.
+ */
+#ifndef WM_H
+#define WM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WM_OK = 0,
+    WM_EINVAL = -1,    /* invalid argument (shape, window, precision, lead) */
+    WM_ENOMEM = -2,    /* device or host allocation failed                  */
+    WM_EAGAIN = -3,    /* not ready yet (serving: request still running)    */
+    WM_EHIP = -4,      /* a HIP runtime call failed                         */
+    WM_ENOTFOUND = -5  /* unknown request id                                */
+} wm_status;
+
+typedef enum {
+    WM_F32 = 0,        /* float32 operands, float32 accumulation            */
+    WM_BF16 = 1,       /* bfloat16 operands (RNE), float32 accumulation     */
+    WM_FP8_E4M3 = 2    /* OCP e4m3 operands with per-tensor scales          */
+} wm_precision;
+
+/* Latent grid and attention window.  Windows are odd and no larger than
+ * their axis.  periodic_mask: bit0 = Z, bit1 = Y, bit2 = X; the paper's
+ * setting is 0x4 -- longitude wraps around the sphere (its own circular
+ * padding), latitude and level windows keep their size and shift inward at
+ * the borders (NATTEN's border behaviour, "bump attention") (App. A.2). */
+typedef struct {
+    int Z, Y, X;
+    int C, heads;
+    int Kz, Ky, Kx;
+    unsigned periodic_mask;
+} wm_grid;
+
+typedef struct wm_ctx wm_ctx;
+typedef struct wm_processor wm_processor;
+typedef struct wm_server wm_server;
+
+/* Message of the last failing call on this thread ("" if none).  The
+ * string is owned by the library and valid until the next call. */
+const char *wm_last_error(void);
+
+/* Library version string (static storage). */
+const char *wm_version(void);
+
+/* Context bound to one HIP device.  It owns a workspace that grows on
+ * demand to hold a block's intermediates for the largest batch seen.
+ * The caller destroys it after all work enqueued through it has finished. */
+int wm_ctx_create(int device, wm_ctx **out);
+void wm_ctx_destroy(wm_ctx *ctx);
+
+/* Kernel timing.  While enabled, every kernel a block launches is
+ * bracketed by HIP events recorded on the stream it is launched on.
+ * wm_prof_collect waits for the recorded events, ADDS each kernel kind's
+ * total milliseconds and launch count into ms[kind] and counts[kind]
+ * (kinds 0..6: LN1, QKV projection, neighborhood attention, output
+ * projection, LN2, MLP1, MLP2; arrays of nkinds entries, either may be
+ * NULL) and clears the records. */
+int wm_prof_enable(wm_ctx *ctx, int on);
+int wm_prof_collect(wm_ctx *ctx, double *ms, long long *counts, int nkinds);
+
+/* Neighborhood index tables of a grid (Sec. 2.1 NATTEN; App. A.2).
+ * dev_out: device int32[2*(Z+Y+X)].  Entries [0, Z+Y+X) are, per axis in
+ * the order Z, Y, X, the first key coordinate of every position's window
+ * (clamped axis: min(max(i-r, 0), N-K); periodic axis: (i-r) mod N); the
+ * window is that coordinate plus t = 0..K-1 (mod N when periodic).
+ * Entries [Z+Y+X, 2*(Z+Y+X)) are the bias-table index (offset + K - 1) of
+ * the first key of that window; it grows by one with t.  Written by a
+ * kernel with the same index functions the attention kernels use. */
+int wm_nat_indices(const wm_grid *g, int *dev_out, void *stream);
+
+/* 3-D neighborhood attention with relative-position bias (Sec. 2.1 NATTEN;
+ * App. A.2 circular padding and bump attention).  For every state b,
+ * token n and head h:
+ *   s(n,m) = q_h(n).k_h(m) / sqrt(d) + rpb[h][dz+Kz-1][dy+Ky-1][dx+Kx-1]
+ *   out_h(n) = sum over m in the window of n of softmax_m(s) v_h(m)
+ * with (dz,dy,dx) = key - query offsets (periodic axes: t - r).
+ * q, k, v, out: device [B][Z*Y*X][heads][d] in float32 (WM_F32) or
+ * bfloat16 (WM_BF16); rpb: device float32 [heads][2Kz-1][2Ky-1][2Kx-1].
+ * Softmax max and sum are float32.  WM_FP8_E4M3 is rejected here (FP8 is
+ * a processor precision).  Uses the context workspace. */
+int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec,
+                   const void *q, const void *k, const void *v,
+                   const float *rpb, void *out, void *stream);
+
+/* LayerNorm of M rows of C float32 values, float32 statistics with biased
+ * variance (the block's two norms; the pre-norm vision-transformer layout
+ * the paper builds on, Sec. 2.1):
+ *   out[m][c] = (x[m][c] - mean_m) / sqrt(var_m + eps) * gamma[c] + beta[c]
+ * x: device float32 [M][C]; gamma, beta: device float32 [C]; out: device
+ * [M][C] float32 (WM_F32) or bfloat16 (WM_BF16).  C in {128,256,512,1024}. */
+int wm_layernorm(int M, int C, const float *x, const float *gamma,
+                 const float *beta, float eps, wm_precision out_prec,
+                 void *out, void *stream);
+
+/* One of the block's linear maps with its fused epilogue:
+ *   r[m][n] = sum_k a[m][k] * w[n][k] + bias[n]
+ * a: device [M][K], w: device [N][K] (output-major), both float32 (WM_F32)
+ * or bfloat16 (WM_BF16), float32 accumulation; bias: device float32 [N].
+ * epilogue 0: out[m][n] = r (operand precision); 1: out = GELU(r) with the
+ * exact erf form (operand precision); 2: float32 out[m][n] += r (the
+ * residual update).  N % 64 == 0; K % 64 == 0 (bf16) or % 32 (float32). */
+int wm_linear(int M, int N, int K, wm_precision prec, const void *a,
+              const void *w, const float *bias, int epilogue, void *out,
+              void *stream);
+
+/* A processor: n_blocks pre-norm neighborhood-attention transformer blocks
+ * (Sec. 2.1; App. A.2) with MLP width mlp_ratio*C, uploaded from HOST
+ * float32 parameters in canonical order, per block:
+ *   ln1_g[C] ln1_b[C] w_qkv[C][3C] b_qkv[3C] rpb[H][2Kz-1][2Ky-1][2Kx-1]
+ *   w_o[C][C] b_o[C] ln2_g[C] ln2_b[C] w_1[C][F] b_1[F] w_2[F][C] b_2[C]
+ * Linear maps are [in][out] (y = x W + b); QKV columns are [Q | K | V].
+ * The library copies and converts what it needs (the host array may be
+ * freed on return) and owns the device copy until wm_processor_destroy.
+ * Requires d = C/heads = 32 and C a multiple of 128. */
+int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks,
+                        int mlp_ratio, wm_precision prec,
+                        const float *host_params, wm_processor **out);
+void wm_processor_destroy(wm_processor *p);
+int wm_processor_blocks(const wm_processor *p);
+
+/* One block, in place on x (device float32 [B][Z][Y][X][C]):
+ *   x1 = x + NA(LN1(x) W_qkv + b_qkv) W_o + b_o
+ *   x  = x1 + GELU(LN2(x1) W_1 + b_1) W_2 + b_2
+ * LayerNorm statistics, softmax max/sum and the residual stream are
+ * float32; the contractions run in the processor's precision with float32
+ * accumulation. */
+int wm_processor_block(wm_ctx *ctx, const wm_processor *p, int block, int B,
+                       float *x, void *stream);
+
+/* One processor step: all blocks in order, in place (Sec. 2.1). */
+int wm_processor_step(wm_ctx *ctx, const wm_processor *p, int B, float *x,
+                      void *stream);
+
+/* Greedy latent-rollout schedule (Sec. 2.1, latent rollout): for
+ * lead_hours >= 0 writes floor(L/6) sixes followed by (L mod 6) ones into
+ * HOST steps_out (if non-NULL and cap is large enough) and returns the
+ * number of steps.  Negative lead or too small cap -> WM_EINVAL. */
+int wm_schedule(int lead_hours, int *steps_out, int cap);
+
+/* Latent rollout: run the six-hour processor p6 and the one-hour processor
+ * p1 on x in place following wm_schedule(lead_hours), with no host
+ * synchronisation between steps.  Lead 0 leaves x unchanged. */
+int wm_rollout(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
+               int B, float *x, int lead_hours, void *stream);
+
+/* Relative L2 error ||y - y_ref|| / ||y_ref|| of n values, accumulated in
+ * float64 on the GPU.  y: device float32; y_ref: device float64.  Waits
+ * for the stream and returns the value (negative on error). */
+double wm_relerr_l2(wm_ctx *ctx, const float *y, const double *y_ref,
+                    size_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WM_H */

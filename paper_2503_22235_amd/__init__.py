@@ -1,0 +1,242 @@
+"""Python binding of libwm, the MI355X latent-processor library.
+
+Argument marshalling only: every computation runs in the HIP kernels of
+libwm.so (built in-tree by ``paper_2503_22235_amd.build``).  Function names
+are those of the C ABI in include/wm.h.  Tensor arguments are torch device
+tensors (or raw integer device addresses); streams default to torch's
+current stream.  If the library is missing, every call raises: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "WM_F32", "WM_BF16", "WM_FP8_E4M3", "WmError", "wm_grid", "lib",
+    "wm_version", "wm_ctx_create", "wm_ctx_destroy", "wm_nat_indices",
+    "wm_nat_forward", "wm_layernorm", "wm_linear", "wm_processor_create",
+    "wm_processor_destroy", "wm_processor_block", "wm_processor_step",
+    "wm_schedule", "wm_rollout", "wm_relerr_l2", "grid_of", "LIB_PATH",
+    "wm_prof_enable", "wm_prof_collect", "PROF_KINDS",
+]
+
+WM_F32, WM_BF16, WM_FP8_E4M3 = 0, 1, 2
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwm.so")
+
+
+class WmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libwm error {code}: {msg}")
+        self.code = code
+
+
+class wm_grid(ctypes.Structure):
+    _fields_ = [("Z", ctypes.c_int), ("Y", ctypes.c_int), ("X", ctypes.c_int),
+                ("C", ctypes.c_int), ("heads", ctypes.c_int),
+                ("Kz", ctypes.c_int), ("Ky", ctypes.c_int), ("Kx", ctypes.c_int),
+                ("periodic_mask", ctypes.c_uint)]
+
+
+def grid_of(g) -> wm_grid:
+    """wm_grid from any object with Z, Y, X, C, heads, Kz, Ky, Kx fields."""
+    if isinstance(g, wm_grid):
+        return g
+    return wm_grid(g.Z, g.Y, g.X, g.C, g.heads, g.Kz, g.Ky, g.Kx,
+                   getattr(g, "periodic_mask", 0x4))
+
+
+_LIB = None
+_vp = ctypes.c_void_p
+_int = ctypes.c_int
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "wm_last_error": (ctypes.c_char_p, []),
+    "wm_version": (ctypes.c_char_p, []),
+    "wm_ctx_create": (_int, [_int, ctypes.POINTER(_vp)]),
+    "wm_ctx_destroy": (None, [_vp]),
+    "wm_nat_indices": (_int, [ctypes.POINTER(wm_grid), _vp, _vp]),
+    "wm_nat_forward": (_int, [_vp, ctypes.POINTER(wm_grid), _int, _int, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "wm_layernorm": (_int, [_int, _int, _vp, _vp, _vp, ctypes.c_float, _int, _vp, _vp]),
+    "wm_linear": (_int, [_int, _int, _int, _int, _vp, _vp, _vp, _int, _vp, _vp]),
+    "wm_processor_create": (_int, [_vp, ctypes.POINTER(wm_grid), _int, _int, _int, _vp, ctypes.POINTER(_vp)]),
+    "wm_processor_destroy": (None, [_vp]),
+    "wm_processor_blocks": (_int, [_vp]),
+    "wm_processor_block": (_int, [_vp, _vp, _int, _int, _vp, _vp]),
+    "wm_processor_step": (_int, [_vp, _vp, _int, _vp, _vp]),
+    "wm_schedule": (_int, [_int, ctypes.POINTER(_int), _int]),
+    "wm_rollout": (_int, [_vp, _vp, _vp, _int, _vp, _int, _vp]),
+    "wm_relerr_l2": (ctypes.c_double, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "wm_prof_enable": (_int, [_vp, _int]),
+    "wm_prof_collect": (_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), _int]),
+}
+
+PROF_KINDS = ("ln1", "qkv", "nat", "proj", "ln2", "mlp1", "mlp2")
+
+
+def lib():
+    """The loaded libwm.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with paper_2503_22235_amd.build.build() "
+                "(no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(rc):
+    if rc < 0:
+        raise WmError(rc, lib().wm_last_error().decode())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def wm_version() -> str:
+    return lib().wm_version().decode()
+
+
+class Ctx:
+    def __init__(self, handle):
+        self.handle = handle
+
+    def close(self):
+        if self.handle:
+            lib().wm_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Processor:
+    def __init__(self, handle, grid, n_blocks, prec):
+        self.handle = handle
+        self.grid = grid
+        self.n_blocks = n_blocks
+        self.prec = prec
+
+    def close(self):
+        if self.handle:
+            lib().wm_processor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wm_ctx_create(device: int = 0) -> Ctx:
+    h = _vp()
+    _check(lib().wm_ctx_create(device, ctypes.byref(h)))
+    return Ctx(h.value)
+
+
+def wm_ctx_destroy(ctx: Ctx):
+    ctx.close()
+
+
+def wm_nat_indices(grid, out, stream=None):
+    g = grid_of(grid)
+    return _check(lib().wm_nat_indices(ctypes.byref(g), _ptr(out), _stream(stream)))
+
+
+def wm_nat_forward(ctx, grid, B, prec, q, k, v, rpb, out, stream=None):
+    g = grid_of(grid)
+    return _check(lib().wm_nat_forward(ctx.handle, ctypes.byref(g), B, prec, _ptr(q), _ptr(k),
+                                       _ptr(v), _ptr(rpb), _ptr(out), _stream(stream)))
+
+
+def wm_layernorm(M, C, x, gamma, beta, eps, out_prec, out, stream=None):
+    return _check(lib().wm_layernorm(M, C, _ptr(x), _ptr(gamma), _ptr(beta), eps, out_prec,
+                                     _ptr(out), _stream(stream)))
+
+
+def wm_linear(M, N, K, prec, a, w, bias, epilogue, out, stream=None):
+    return _check(lib().wm_linear(M, N, K, prec, _ptr(a), _ptr(w), _ptr(bias), epilogue,
+                                  _ptr(out), _stream(stream)))
+
+
+def wm_processor_create(ctx, grid, n_blocks, mlp_ratio, prec, host_params) -> Processor:
+    """host_params: numpy float32 array in the canonical parameter order."""
+    import numpy as np
+    hp = np.ascontiguousarray(host_params, dtype=np.float32)
+    g = grid_of(grid)
+    h = _vp()
+    _check(lib().wm_processor_create(ctx.handle, ctypes.byref(g), n_blocks, mlp_ratio, prec,
+                                     hp.ctypes.data, ctypes.byref(h)))
+    return Processor(h.value, g, n_blocks, prec)
+
+
+def wm_processor_destroy(p: Processor):
+    p.close()
+
+
+def wm_processor_block(ctx, p, block, B, x, stream=None):
+    return _check(lib().wm_processor_block(ctx.handle, p.handle, block, B, _ptr(x), _stream(stream)))
+
+
+def wm_processor_step(ctx, p, B, x, stream=None):
+    return _check(lib().wm_processor_step(ctx.handle, p.handle, B, _ptr(x), _stream(stream)))
+
+
+def wm_schedule(lead_hours: int):
+    n = _check(lib().wm_schedule(lead_hours, None, 0))
+    buf = (_int * max(n, 1))()
+    _check(lib().wm_schedule(lead_hours, buf, n))
+    return [buf[i] for i in range(n)]
+
+
+def wm_rollout(ctx, p6, p1, B, x, lead_hours, stream=None):
+    return _check(lib().wm_rollout(ctx.handle, p6.handle, p1.handle, B, _ptr(x), lead_hours,
+                                   _stream(stream)))
+
+
+def wm_prof_enable(ctx, on=True):
+    return _check(lib().wm_prof_enable(ctx.handle, 1 if on else 0))
+
+
+def wm_prof_collect(ctx):
+    """{kind: (total_ms, launches)} of the kernels recorded since the last collect."""
+    n = len(PROF_KINDS)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_longlong * n)()
+    _check(lib().wm_prof_collect(ctx.handle, ms, cnt, n))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(PROF_KINDS)}
+
+
+def wm_relerr_l2(ctx, y, y_ref, n=None, stream=None) -> float:
+    if n is None:
+        n = y.numel()
+    r = lib().wm_relerr_l2(ctx.handle, _ptr(y), _ptr(y_ref), n, _stream(stream))
+    if r < 0:
+        raise WmError(int(r), lib().wm_last_error().decode())
+    return r

@@ -1,0 +1,388 @@
+// C ABI of libwm: contexts, processors, the block / step / rollout launch
+// sequences and the small helpers.  Declarations and contracts: wm.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/wm.h"
+#include "kernels.hpp"
+#include "runtime.hpp"
+
+using namespace wm;
+
+namespace wm {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(WM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int validate_grid(const wm_grid *g, bool need_block) {
+    if (!g) return fail(WM_EINVAL, "grid is NULL");
+    const int N[3] = {g->Z, g->Y, g->X}, K[3] = {g->Kz, g->Ky, g->Kx};
+    const char *nm = "ZYX";
+    for (int a = 0; a < 3; ++a) {
+        if (N[a] < 1) return fail(WM_EINVAL, "axis %c has length %d", nm[a], N[a]);
+        if (K[a] < 1 || K[a] % 2 == 0) return fail(WM_EINVAL, "window on %c must be odd (got %d)", nm[a], K[a]);
+        if (K[a] > N[a]) return fail(WM_EINVAL, "window %d larger than axis %c (%d)", K[a], nm[a], N[a]);
+    }
+    if (g->periodic_mask > 7) return fail(WM_EINVAL, "periodic_mask must be within 0..7");
+    if (g->heads < 1 || g->C != g->heads * 32) return fail(WM_EINVAL, "head dim must be 32 (C=%d heads=%d)", g->C, g->heads);
+    if (need_block && !(g->C == 128 || g->C == 256 || g->C == 512 || g->C == 1024))
+        return fail(WM_EINVAL, "C must be 128, 256, 512 or 1024 (got %d)", g->C);
+    if ((long long)g->Z * g->Y * g->X > (1LL << 30)) return fail(WM_EINVAL, "grid too large");
+    return WM_OK;
+}
+
+int ctx_reserve(wm_ctx *ctx, size_t bytes) {
+    if (bytes <= ctx->ws_bytes) return WM_OK;
+    hipError_t e;
+    if (ctx->ws) {
+        // In-flight work may still use the old buffer.
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    if ((e = hipMalloc(&ctx->ws, bytes)) != hipSuccess) {
+        ctx->ws = nullptr;
+        (void)hipGetLastError();
+        return fail(WM_ENOMEM, "workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+    }
+    ctx->ws_bytes = bytes;
+    return WM_OK;
+}
+
+}  // namespace wm
+
+static uint16_t host_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+extern "C" {
+
+const char *wm_last_error(void) { return g_err.c_str(); }
+
+const char *wm_version(void) { return "libwm 0.1 (gfx950)"; }
+
+int wm_ctx_create(int device, wm_ctx **out) {
+    if (!out) return fail(WM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n) return fail(WM_EINVAL, "device %d out of range (%d devices)", device, n);
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    wm_ctx *c = new (std::nothrow) wm_ctx();
+    if (!c) return fail(WM_ENOMEM, "context allocation");
+    c->device = device;
+    if ((e = hipMalloc(&c->small, 4096)) != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipMalloc(small)");
+    }
+    *out = c;
+    return WM_OK;
+}
+
+void wm_ctx_destroy(wm_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->small) (void)hipFree(ctx->small);
+    delete ctx;
+}
+
+int wm_prof_enable(wm_ctx *ctx, int on) {
+    if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
+    ctx->prof = on != 0;
+    return WM_OK;
+}
+
+int wm_prof_collect(wm_ctx *ctx, double *ms, long long *counts, int nkinds) {
+    if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
+    if (nkinds < 0) return fail(WM_EINVAL, "negative nkinds");
+    hipError_t e;
+    int rc = WM_OK;
+    for (auto &r : ctx->recs) {
+        if (rc == WM_OK) {
+            float t = 0.f;
+            if ((e = hipEventSynchronize(r.b)) != hipSuccess) rc = hip_fail(e, "hipEventSynchronize");
+            else if ((e = hipEventElapsedTime(&t, r.a, r.b)) != hipSuccess) rc = hip_fail(e, "hipEventElapsedTime");
+            else if (r.kind < nkinds) {
+                if (ms) ms[r.kind] += t;
+                if (counts) counts[r.kind] += 1;
+            }
+        }
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    return rc;
+}
+
+int wm_nat_indices(const wm_grid *g, int *dev_out, void *stream) {
+    int rc = validate_grid(g, false);
+    if (rc) return rc;
+    if (!dev_out) return fail(WM_EINVAL, "dev_out is NULL");
+    hipError_t e = launch_nat_indices(g->Z, g->Y, g->X, g->Kz, g->Ky, g->Kx, g->periodic_mask, dev_out,
+                                      (hipStream_t)stream);
+    return e == hipSuccess ? WM_OK : hip_fail(e, "nat_indices launch");
+}
+
+int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec, const void *q, const void *k,
+                   const void *v, const float *rpb, void *out, void *stream) {
+    int rc = validate_grid(g, false);
+    if (rc) return rc;
+    if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
+    if (B < 0) return fail(WM_EINVAL, "negative batch");
+    if (prec != WM_F32 && prec != WM_BF16) return fail(WM_EINVAL, "wm_nat_forward takes WM_F32 or WM_BF16");
+    if (B == 0) return WM_OK;
+    if (!q || !k || !v || !rpb || !out) return fail(WM_EINVAL, "NULL tensor");
+    const long T = (long)g->Z * g->Y * g->X;
+    NatArgs a{};
+    a.q = q; a.k = k; a.v = v;
+    a.bs = T * g->C; a.ts = g->C; a.hs = 32;
+    a.out = out; a.obs = T * g->C; a.ots = g->C;
+    a.rpb = rpb;
+    a.qscale = LOG2E / std::sqrt(32.0f);
+    a.bscale = LOG2E;
+    a.B = B; a.Z = g->Z; a.Y = g->Y; a.X = g->X; a.H = g->heads;
+    a.Kz = g->Kz; a.Ky = g->Ky; a.Kx = g->Kx; a.periodic = g->periodic_mask;
+    hipError_t e = launch_nat(a, prec == WM_BF16, (hipStream_t)stream);
+    return e == hipSuccess ? WM_OK : hip_fail(e, "nat launch");
+}
+
+int wm_layernorm(int M, int C, const float *x, const float *gamma, const float *beta, float eps,
+                 wm_precision out_prec, void *out, void *stream) {
+    if (M < 0) return fail(WM_EINVAL, "negative M");
+    if (!(C == 128 || C == 256 || C == 512 || C == 1024)) return fail(WM_EINVAL, "C must be 128/256/512/1024");
+    if (out_prec != WM_F32 && out_prec != WM_BF16) return fail(WM_EINVAL, "out precision must be F32 or BF16");
+    if (M == 0) return WM_OK;
+    if (!x || !gamma || !beta || !out) return fail(WM_EINVAL, "NULL tensor");
+    hipError_t e = launch_layernorm(x, gamma, beta, out, out_prec == WM_BF16, M, C, eps, (hipStream_t)stream);
+    return e == hipSuccess ? WM_OK : hip_fail(e, "layernorm launch");
+}
+
+int wm_linear(int M, int N, int K, wm_precision prec, const void *a, const void *w, const float *bias,
+              int epilogue, void *out, void *stream) {
+    if (M < 0 || N <= 0 || K <= 0) return fail(WM_EINVAL, "bad GEMM shape");
+    if (prec != WM_F32 && prec != WM_BF16) return fail(WM_EINVAL, "precision must be F32 or BF16");
+    if (N % 64) return fail(WM_EINVAL, "N must be a multiple of 64");
+    if (K % (prec == WM_BF16 ? 64 : 32)) return fail(WM_EINVAL, "K must be a multiple of %d", prec == WM_BF16 ? 64 : 32);
+    if (epilogue < 0 || epilogue > 2) return fail(WM_EINVAL, "epilogue must be 0, 1 or 2");
+    if (M == 0) return WM_OK;
+    if (!a || !w || !bias || !out) return fail(WM_EINVAL, "NULL tensor");
+    EpiArgs ep{};
+    ep.bias = bias;
+    EpiKind kind = EPI_STORE;
+    if (epilogue == 1) { kind = EPI_GELU; ep.out = out; }
+    else if (epilogue == 2) { kind = EPI_RESID; ep.resid = (float *)out; }
+    else ep.out = out;
+    hipError_t e = launch_gemm(a, w, M, N, K, prec == WM_BF16, kind, ep, (hipStream_t)stream);
+    return e == hipSuccess ? WM_OK : hip_fail(e, "gemm launch");
+}
+
+int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_ratio, wm_precision prec,
+                        const float *host_params, wm_processor **out) {
+    if (!out) return fail(WM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
+    int rc = validate_grid(g, true);
+    if (rc) return rc;
+    if (n_blocks < 1 || n_blocks > 64) return fail(WM_EINVAL, "n_blocks must be 1..64");
+    if (mlp_ratio < 1 || mlp_ratio > 8) return fail(WM_EINVAL, "mlp_ratio must be 1..8");
+    if (prec != WM_F32 && prec != WM_BF16) return fail(WM_EINVAL, "processor precision %d not supported", (int)prec);
+    if (!host_params) return fail(WM_EINVAL, "host_params is NULL");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+
+    wm_processor *p = new (std::nothrow) wm_processor();
+    if (!p) return fail(WM_ENOMEM, "processor allocation");
+    p->g = *g;
+    p->nb = n_blocks;
+    p->mlp = mlp_ratio;
+    p->prec = prec;
+    p->device = ctx->device;
+    const int C = g->C, F = C * mlp_ratio, H = g->heads;
+    const size_t nrpb = (size_t)H * (2 * g->Kz - 1) * (2 * g->Ky - 1) * (2 * g->Kx - 1);
+    const size_t esz = prec == WM_BF16 ? 2 : 4;
+    // Device image per block: float32 vectors, then the four transposed weights.
+    const size_t nvec = 2 * C + 3 * C + nrpb + C + 2 * C + F + C;
+    const size_t nw = (size_t)3 * C * C + (size_t)C * C + (size_t)F * C * 2;
+    auto align = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t blk_bytes = align(nvec * 4) + align(nw * esz) + 4 * 256;
+    p->bytes = blk_bytes * n_blocks;
+    if ((e = hipMalloc(&p->mem, p->bytes)) != hipSuccess) {
+        delete p;
+        (void)hipGetLastError();
+        return fail(WM_ENOMEM, "processor weights (%zu bytes): %s", p->bytes, hipGetErrorString(e));
+    }
+    std::vector<unsigned char> img(blk_bytes);
+    const float *src = host_params;
+    for (int bI = 0; bI < n_blocks; ++bI) {
+        std::memset(img.data(), 0, img.size());
+        unsigned char *dev = (unsigned char *)p->mem + blk_bytes * bI;
+        BlockWeights &bw = p->blk[bI];
+        size_t off = 0;
+        auto put_vec = [&](const float *s, size_t n, float scale, const float **dst) {
+            float *d = (float *)(img.data() + off);
+            for (size_t i = 0; i < n; ++i) d[i] = s[i] * scale;
+            *dst = (const float *)(dev + off);
+            off += n * 4;
+        };
+        auto put_wt = [&](const float *s, int in, int outn, const void **dst) {
+            off = align(off);
+            // source [in][out] -> device [out][in]
+            if (esz == 2) {
+                uint16_t *d = (uint16_t *)(img.data() + off);
+                for (int o = 0; o < outn; ++o)
+                    for (int i = 0; i < in; ++i) d[(size_t)o * in + i] = host_bf16(s[(size_t)i * outn + o]);
+            } else {
+                float *d = (float *)(img.data() + off);
+                for (int o = 0; o < outn; ++o)
+                    for (int i = 0; i < in; ++i) d[(size_t)o * in + i] = s[(size_t)i * outn + o];
+            }
+            *dst = dev + off;
+            off += (size_t)in * outn * esz;
+        };
+        const float *ln1_g = src; src += C;
+        const float *ln1_b = src; src += C;
+        const float *w_qkv = src; src += (size_t)C * 3 * C;
+        const float *b_qkv = src; src += 3 * C;
+        const float *rpb = src; src += nrpb;
+        const float *w_o = src; src += (size_t)C * C;
+        const float *b_o = src; src += C;
+        const float *ln2_g = src; src += C;
+        const float *ln2_b = src; src += C;
+        const float *w_1 = src; src += (size_t)C * F;
+        const float *b_1 = src; src += F;
+        const float *w_2 = src; src += (size_t)F * C;
+        const float *b_2 = src; src += C;
+        put_vec(ln1_g, C, 1.f, &bw.ln1_g);
+        put_vec(ln1_b, C, 1.f, &bw.ln1_b);
+        put_vec(b_qkv, 3 * C, 1.f, &bw.b_qkv);
+        put_vec(rpb, nrpb, LOG2E, &bw.rpb_log2);
+        put_vec(b_o, C, 1.f, &bw.b_o);
+        put_vec(ln2_g, C, 1.f, &bw.ln2_g);
+        put_vec(ln2_b, C, 1.f, &bw.ln2_b);
+        put_vec(b_1, F, 1.f, &bw.b_1);
+        put_vec(b_2, C, 1.f, &bw.b_2);
+        put_wt(w_qkv, C, 3 * C, &bw.w_qkv);
+        put_wt(w_o, C, C, &bw.w_o);
+        put_wt(w_1, C, F, &bw.w_1);
+        put_wt(w_2, F, C, &bw.w_2);
+        if ((e = hipMemcpy(dev, img.data(), blk_bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+            (void)hipFree(p->mem);
+            delete p;
+            return hip_fail(e, "weight upload");
+        }
+    }
+    *out = p;
+    return WM_OK;
+}
+
+void wm_processor_destroy(wm_processor *p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->mem) (void)hipFree(p->mem);
+    delete p;
+}
+
+int wm_processor_blocks(const wm_processor *p) { return p ? p->nb : fail(WM_EINVAL, "processor is NULL"); }
+
+int wm_processor_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, void *stream) {
+    if (!ctx || !p) return fail(WM_EINVAL, "NULL ctx or processor");
+    if (block < 0 || block >= p->nb) return fail(WM_EINVAL, "block %d out of range (%d blocks)", block, p->nb);
+    if (B < 0) return fail(WM_EINVAL, "negative batch");
+    if (B == 0) return WM_OK;
+    if (!x) return fail(WM_EINVAL, "x is NULL");
+    int rc = reserve_block_workspace(ctx, p, B);
+    if (rc) return rc;
+    return run_block(ctx, p, block, B, x, (hipStream_t)stream);
+}
+
+int wm_processor_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, void *stream) {
+    if (!ctx || !p) return fail(WM_EINVAL, "NULL ctx or processor");
+    if (B < 0) return fail(WM_EINVAL, "negative batch");
+    if (B == 0) return WM_OK;
+    if (!x) return fail(WM_EINVAL, "x is NULL");
+    int rc = reserve_block_workspace(ctx, p, B);
+    if (rc) return rc;
+    return run_step(ctx, p, B, x, (hipStream_t)stream);
+}
+
+int wm_schedule(int lead_hours, int *steps_out, int cap) {
+    if (lead_hours < 0) return fail(WM_EINVAL, "negative lead time %d", lead_hours);
+    const int n = greedy_schedule(lead_hours, nullptr, 0);
+    if (steps_out) {
+        if (cap < n) return fail(WM_EINVAL, "schedule needs %d entries, cap is %d", n, cap);
+        greedy_schedule(lead_hours, steps_out, cap);
+    }
+    return n;
+}
+
+int wm_rollout(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1, int B, float *x, int lead_hours,
+               void *stream) {
+    if (!ctx || !p6 || !p1) return fail(WM_EINVAL, "NULL ctx or processor");
+    if (lead_hours < 0) return fail(WM_EINVAL, "negative lead time %d", lead_hours);
+    if (B < 0) return fail(WM_EINVAL, "negative batch");
+    if (std::memcmp(&p6->g, &p1->g, sizeof(wm_grid)) != 0) return fail(WM_EINVAL, "processors have different grids");
+    if (B == 0 || lead_hours == 0) return WM_OK;
+    if (!x) return fail(WM_EINVAL, "x is NULL");
+    int rc = reserve_block_workspace(ctx, p6, B);
+    if (rc) return rc;
+    rc = reserve_block_workspace(ctx, p1, B);
+    if (rc) return rc;
+    std::vector<int> steps(greedy_schedule(lead_hours, nullptr, 0));
+    greedy_schedule(lead_hours, steps.data(), (int)steps.size());
+    for (int s : steps) {
+        rc = run_step(ctx, s == 6 ? p6 : p1, B, x, (hipStream_t)stream);
+        if (rc) return rc;
+    }
+    return WM_OK;
+}
+
+double wm_relerr_l2(wm_ctx *ctx, const float *y, const double *y_ref, size_t n, void *stream) {
+    if (!ctx || !y || !y_ref) return (double)fail(WM_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if ((e = hipMemsetAsync(ctx->small, 0, 2 * sizeof(double), s)) != hipSuccess)
+        return (double)hip_fail(e, "memset");
+    if ((e = launch_relerr(y, y_ref, n, (double *)ctx->small, s)) != hipSuccess) return (double)hip_fail(e, "relerr");
+    double h[2];
+    if ((e = hipMemcpyAsync(h, ctx->small, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return (double)hip_fail(e, "copy");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return (double)hip_fail(e, "sync");
+    if (h[1] == 0.0) return h[0] == 0.0 ? 0.0 : INFINITY;
+    return std::sqrt(h[0] / h[1]);
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Shared device-side types and helpers of libwm (gfx950 / CDNA4 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace wm {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int WAVE = 64;
+constexpr float LOG2E = 1.4426950408889634f;
+
+// float32 -> bfloat16 bits, round to nearest even (NaN kept quiet).
+__device__ __forceinline__ unsigned short f2bf_bits(float f) {
+    unsigned int u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return (unsigned short)((u >> 16) | 0x0040u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf_bits2f(unsigned short b) {
+    return __uint_as_float(((unsigned int)b) << 16);
+}
+__device__ __forceinline__ bf16 f2bf(float f) {
+    unsigned short b = f2bf_bits(f);
+    return __builtin_bit_cast(bf16, b);
+}
+__device__ __forceinline__ float bf2f(bf16 b) {
+    return bf_bits2f(__builtin_bit_cast(unsigned short, b));
+}
+
+// Loads/stores of element type T as float.
+template <typename T> struct Elt;
+template <> struct Elt<float> {
+    static __device__ __forceinline__ float ld(const float *p) { return *p; }
+    static __device__ __forceinline__ void st(float *p, float v) { *p = v; }
+};
+template <> struct Elt<bf16> {
+    static __device__ __forceinline__ float ld(const bf16 *p) { return bf2f(*p); }
+    static __device__ __forceinline__ void st(bf16 *p, float v) { *p = f2bf(v); }
+};
+
+// Wave-wide reductions (64 lanes).
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Neighborhood windows (WeatherMesh-3 Sec. 2.1 NATTEN; App. A.2).  One axis
+// of length n with odd window k, r = (k-1)/2.
+//   clamped axis (lat, level): the window keeps k entries and shifts inward
+//     at the borders: start = min(max(i-r, 0), n-k); keys start+t.
+//   periodic axis (lon): keys (i-r+t) mod n.
+// The bias-table index of key t is (key - query offset) + k - 1; on a
+// periodic axis the offset is t - r.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ int win_start(int i, int n, int k, bool periodic) {
+    int r = (k - 1) >> 1;
+    if (periodic) {
+        int s = (i - r) % n;
+        return s < 0 ? s + n : s;
+    }
+    int s = i - r;
+    s = s < 0 ? 0 : s;
+    return s > n - k ? n - k : s;
+}
+// Bias index of the first key (t = 0) of position i's window.
+__host__ __device__ __forceinline__ int win_bias0(int i, int n, int k, bool periodic) {
+    if (periodic) return k - 1 - ((k - 1) >> 1);          // offset -r  ->  -r + k - 1
+    return win_start(i, n, k, false) - i + k - 1;
+}
+
+}  // namespace wm

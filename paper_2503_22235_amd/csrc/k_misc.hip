@@ -1,0 +1,144 @@
+// LayerNorm, neighborhood index tables and the float64 error norm.
+#include "kernels.hpp"
+
+namespace wm {
+namespace {
+
+// One wave per token row; C = 64 * VPT.  Each lane holds VPT values, read
+// as float4 (or float2) chunks interleaved across the wave so every load
+// instruction covers one contiguous span of the row.  Statistics are
+// float32 with a two-pass (mean, then centred squares) variance kept in
+// registers.
+template <int VPT, bool OBF>
+__global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict__ x,
+                                                        const float *__restrict__ gamma,
+                                                        const float *__restrict__ beta,
+                                                        void *__restrict__ out, int M, float eps) {
+    constexpr int C = VPT * 64;
+    constexpr int W = VPT >= 4 ? 4 : VPT;     // vector width
+    constexpr int NV = VPT / W;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= M) return;
+    const int lane = threadIdx.x & 63;
+    const float *xr = x + (size_t)row * C;
+    float v[VPT];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int base = (j * 64 + lane) * W;
+        if constexpr (W == 4) {
+            const float4 t = *(const float4 *)(xr + base);
+            v[4 * j] = t.x; v[4 * j + 1] = t.y; v[4 * j + 2] = t.z; v[4 * j + 3] = t.w;
+        } else {
+            const float2 t = *(const float2 *)(xr + base);
+            v[2 * j] = t.x; v[2 * j + 1] = t.y;
+        }
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) s += v[i];
+    const float mean = wave_sum(s) * (1.0f / C);
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+        const float d = v[i] - mean;
+        q += d * d;
+    }
+    const float var = wave_sum(q) * (1.0f / C);
+    const float rstd = 1.0f / sqrtf(var + eps);
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int base = (j * 64 + lane) * W;
+        float y[W];
+#pragma unroll
+        for (int t = 0; t < W; ++t) y[t] = (v[W * j + t] - mean) * rstd * gamma[base + t] + beta[base + t];
+        if constexpr (OBF) {
+            bf16 *o = (bf16 *)out + (size_t)row * C + base;
+            if constexpr (W == 4) {
+                uint2 u;
+                u.x = (unsigned)f2bf_bits(y[0]) | ((unsigned)f2bf_bits(y[1]) << 16);
+                u.y = (unsigned)f2bf_bits(y[2]) | ((unsigned)f2bf_bits(y[3]) << 16);
+                *(uint2 *)o = u;
+            } else {
+                *(unsigned *)o = (unsigned)f2bf_bits(y[0]) | ((unsigned)f2bf_bits(y[1]) << 16);
+            }
+        } else {
+            float *o = (float *)out + (size_t)row * C + base;
+            if constexpr (W == 4) *(float4 *)o = make_float4(y[0], y[1], y[2], y[3]);
+            else *(float2 *)o = make_float2(y[0], y[1]);
+        }
+    }
+}
+
+template <int VPT>
+hipError_t ln_launch(const float *x, const float *g, const float *b, void *out, bool obf, int M, float eps,
+                     hipStream_t s) {
+    const int grid = (M + 3) / 4;
+    if (obf) layernorm_kernel<VPT, true><<<grid, 256, 0, s>>>(x, g, b, out, M, eps);
+    else layernorm_kernel<VPT, false><<<grid, 256, 0, s>>>(x, g, b, out, M, eps);
+    return hipGetLastError();
+}
+
+__global__ void nat_indices_kernel(int Z, int Y, int X, int Kz, int Ky, int Kx, unsigned periodic,
+                                   int *out) {
+    const int n = Z + Y + X;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int pos, N, K;
+    bool per;
+    if (i < Z) { pos = i; N = Z; K = Kz; per = periodic & 1; }
+    else if (i < Z + Y) { pos = i - Z; N = Y; K = Ky; per = (periodic >> 1) & 1; }
+    else { pos = i - Z - Y; N = X; K = Kx; per = (periodic >> 2) & 1; }
+    out[i] = win_start(pos, N, K, per);
+    out[n + i] = win_bias0(pos, N, K, per);
+}
+
+__global__ __launch_bounds__(256) void relerr_kernel(const float *__restrict__ y, const double *__restrict__ r,
+                                                     size_t n, double *acc) {
+    double se = 0.0, sr = 0.0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const double rv = r[i];
+        const double d = (double)y[i] - rv;
+        se += d * d;
+        sr += rv * rv;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        se += __shfl_xor(se, o, 64);
+        sr += __shfl_xor(sr, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(acc, se);
+        atomicAdd(acc + 1, sr);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_layernorm(const float *x, const float *gamma, const float *beta, void *out, bool out_bf16,
+                            int M, int C, float eps, hipStream_t stream) {
+    if (M <= 0) return hipSuccess;
+    switch (C) {
+    case 128: return ln_launch<2>(x, gamma, beta, out, out_bf16, M, eps, stream);
+    case 256: return ln_launch<4>(x, gamma, beta, out, out_bf16, M, eps, stream);
+    case 512: return ln_launch<8>(x, gamma, beta, out, out_bf16, M, eps, stream);
+    case 1024: return ln_launch<16>(x, gamma, beta, out, out_bf16, M, eps, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_nat_indices(int Z, int Y, int X, int Kz, int Ky, int Kx, unsigned periodic, int *out,
+                              hipStream_t stream) {
+    const int n = Z + Y + X;
+    nat_indices_kernel<<<(n + 255) / 256, 256, 0, stream>>>(Z, Y, X, Kz, Ky, Kx, periodic, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_relerr(const float *y, const double *r, size_t n, double *acc, hipStream_t stream) {
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks == 0) blocks = 1;
+    relerr_kernel<<<(unsigned)blocks, 256, 0, stream>>>(y, r, n, acc);
+    return hipGetLastError();
+}
+
+}  // namespace wm

@@ -1,0 +1,68 @@
+// Host-side launchers of the libwm kernels (all enqueue on `stream`).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "common.hpp"
+
+namespace wm {
+
+// --- LayerNorm over the channel axis, float32 statistics -----------------
+// out[m][c] = (x[m][c] - mu_m) / sqrt(var_m + eps) * gamma[c] + beta[c]
+// with biased variance; out element type is float or bf16.
+hipError_t launch_layernorm(const float *x, const float *gamma, const float *beta,
+                            void *out, bool out_bf16, int M, int C, float eps,
+                            hipStream_t stream);
+
+// --- GEMM D[m][n] = sum_k A[m][k] * W[n][k] with fused epilogues ---------
+enum EpiKind : int {
+    EPI_QKV = 0,    // +bias; Q columns * qscale; scatter to head-major [3][H][M][32]
+    EPI_GELU = 1,   // gelu(+bias) -> out [M][N]
+    EPI_RESID = 2,  // resid[m][n] += acc + bias (float32 in place)
+    EPI_STORE = 3   // +bias -> out [M][N]
+};
+struct EpiArgs {
+    const float *bias;  // [N]
+    void *out;          // EPI_QKV / EPI_GELU / EPI_STORE output
+    float *resid;       // EPI_RESID target
+    int C, H;           // EPI_QKV: model width and heads (d = 32)
+    float qscale;       // EPI_QKV: factor on Q columns
+};
+// A: [M][K], W: [N][K], both bf16 (a_bf16) or float32.  Output element
+// type follows the operands (bf16 or float) except EPI_RESID (float32).
+// Requires N % 128 == 0 (N % 64 for small N) and K % 64 == 0 (bf16) /
+// K % 32 == 0 (float32).
+hipError_t launch_gemm(const void *A, const void *W, int M, int N, int K, bool a_bf16,
+                       EpiKind epi, const EpiArgs &ep, hipStream_t stream);
+
+// --- 3-D neighborhood attention ------------------------------------------
+struct NatArgs {
+    const void *q, *k, *v;  // element (b,t,h,e) at base + b*bs + t*ts + h*hs + e
+    long bs, ts, hs;        // strides of q/k/v in elements
+    void *out;              // element (b,t,h,e) at out + b*obs + t*ots + h*32 + e
+    long obs, ots;
+    const float *rpb;       // [H][2Kz-1][2Ky-1][2Kx-1]
+    float qscale;           // scores: (q.k) * qscale + rpb * bscale, in log2 units
+    float bscale;
+    int B, Z, Y, X, H;
+    int Kz, Ky, Kx;
+    unsigned periodic;
+};
+// Picks the LDS-tiled bf16 kernel when it applies, else the generic one.
+hipError_t launch_nat(const NatArgs &a, bool bf16, hipStream_t stream);
+hipError_t launch_nat_generic(const NatArgs &a, bool bf16, hipStream_t stream);
+// LDS bytes of the tiled bf16 kernel for these arguments (0: not applicable).
+size_t nat_tile_lds_bytes(const NatArgs &a);
+hipError_t launch_nat_tile(const NatArgs &a, hipStream_t stream);
+
+// --- index tables (same window functions as the attention kernels) ------
+hipError_t launch_nat_indices(int Z, int Y, int X, int Kz, int Ky, int Kx,
+                              unsigned periodic, int *out, hipStream_t stream);
+
+// --- float64 relative-error partial sums: acc[0] += sum (y-r)^2, acc[1] += sum r^2
+hipError_t launch_relerr(const float *y, const double *r, size_t n, double *acc,
+                         hipStream_t stream);
+
+// --- layout copies for the standalone attention entry point ---------------
+}  // namespace wm

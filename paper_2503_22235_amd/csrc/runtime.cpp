@@ -1,0 +1,138 @@
+// Launch sequences of a processor block and step, and the greedy schedule.
+#include <cmath>
+
+#include "runtime.hpp"
+
+namespace wm {
+
+size_t block_workspace_bytes(const wm_processor *p, int B) {
+    const size_t M = (size_t)B * p->g.Z * p->g.Y * p->g.X;
+    const size_t C = p->g.C, F = C * p->mlp;
+    const size_t esz = p->prec == WM_BF16 ? 2 : 4;
+    const size_t big = (3 * C > F ? 3 * C : F);
+    return M * (C + big) * esz + 512;
+}
+
+int reserve_block_workspace(wm_ctx *ctx, const wm_processor *p, int B) {
+    return ctx_reserve(ctx, block_workspace_bytes(p, B));
+}
+
+static hipEvent_t pool_get(wm_ctx *ctx) {
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int prof_begin(wm_ctx *ctx, hipStream_t s, int kind) {
+    if (!ctx->prof) return WM_OK;
+    ProfRec r{kind, pool_get(ctx), pool_get(ctx)};
+    if (!r.a || !r.b) return fail(WM_EHIP, "hipEventCreate failed");
+    hipError_t e = hipEventRecord(r.a, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ctx->recs.push_back(r);
+    return WM_OK;
+}
+
+int prof_end(wm_ctx *ctx, hipStream_t s) {
+    if (!ctx->prof || ctx->recs.empty()) return WM_OK;
+    hipError_t e = hipEventRecord(ctx->recs.back().b, s);
+    return e == hipSuccess ? WM_OK : hip_fail(e, "hipEventRecord");
+}
+
+// One pre-norm block on the float32 residual stream x [B*T][C]:
+//   u = LN1(x); [q|k|v] = u W_qkv + b (Q pre-scaled by log2(e)/sqrt(d),
+//   written head-major); o = NA(q, k, v); x += o W_o + b_o;
+//   w = LN2(x); h = GELU(w W_1 + b_1); x += h W_2 + b_2.
+// u, o and w share one buffer; qkv and h share the other.
+int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s) {
+    const wm_grid &g = p->g;
+    const BlockWeights &w = p->blk[block];
+    const long T = (long)g.Z * g.Y * g.X;
+    const int M = (int)(B * T);
+    const int C = g.C, F = C * p->mlp, H = g.heads;
+    const bool bf = p->prec == WM_BF16;
+    const size_t esz = bf ? 2 : 4;
+    char *act = (char *)ctx->ws;
+    char *big = act + (((size_t)M * C * esz + 255) & ~(size_t)255);
+    hipError_t e;
+
+    int rc;
+#define WM_TIMED(kind, call, what)                                  \
+    if ((rc = prof_begin(ctx, s, kind)) != WM_OK) return rc;        \
+    if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
+    if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
+    WM_TIMED(PK_LN1, launch_layernorm(x, w.ln1_g, w.ln1_b, act, bf, M, C, 1e-5f, s), "LN1")
+    EpiArgs ep{};
+    ep.bias = w.b_qkv;
+    ep.out = big;
+    ep.C = C;
+    ep.H = H;
+    ep.qscale = LOG2E / std::sqrt(32.0f);
+    WM_TIMED(PK_QKV, launch_gemm(act, w.w_qkv, M, 3 * C, C, bf, EPI_QKV, ep, s), "QKV")
+
+    NatArgs na{};
+    const size_t plane = (size_t)H * M * 32 * esz;
+    na.q = big;
+    na.k = big + plane;
+    na.v = big + 2 * plane;
+    na.bs = T * 32;
+    na.ts = 32;
+    na.hs = (long)M * 32;
+    na.out = act;
+    na.obs = T * C;
+    na.ots = C;
+    na.rpb = w.rpb_log2;
+    na.qscale = 1.0f;
+    na.bscale = 1.0f;
+    na.B = B; na.Z = g.Z; na.Y = g.Y; na.X = g.X; na.H = H;
+    na.Kz = g.Kz; na.Ky = g.Ky; na.Kx = g.Kx; na.periodic = g.periodic_mask;
+    WM_TIMED(PK_NA, launch_nat(na, bf, s), "NA")
+
+    EpiArgs er{};
+    er.bias = w.b_o;
+    er.resid = x;
+    WM_TIMED(PK_PROJ, launch_gemm(act, w.w_o, M, C, C, bf, EPI_RESID, er, s), "proj")
+    WM_TIMED(PK_LN2, launch_layernorm(x, w.ln2_g, w.ln2_b, act, bf, M, C, 1e-5f, s), "LN2")
+    EpiArgs eg{};
+    eg.bias = w.b_1;
+    eg.out = big;
+    WM_TIMED(PK_MLP1, launch_gemm(act, w.w_1, M, F, C, bf, EPI_GELU, eg, s), "MLP1")
+    EpiArgs e2{};
+    e2.bias = w.b_2;
+    e2.resid = x;
+    WM_TIMED(PK_MLP2, launch_gemm(big, w.w_2, M, C, F, bf, EPI_RESID, e2, s), "MLP2")
+#undef WM_TIMED
+    return WM_OK;
+}
+
+int run_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, hipStream_t s) {
+    for (int b = 0; b < p->nb; ++b) {
+        int rc = run_block(ctx, p, b, B, x, s);
+        if (rc) return rc;
+    }
+    return WM_OK;
+}
+
+// Sec. 2.1, latent rollout: the six-hour and one-hour processors are called
+// until the lead time is reached by a greedy schedule -- as many six-hour
+// steps as fit, then one-hour steps.
+int greedy_schedule(int lead_hours, int *out, int cap) {
+    int n = 0;
+    int left = lead_hours;
+    const int sizes[2] = {6, 1};
+    for (int size : sizes) {
+        while (left >= size) {
+            if (out && n < cap) out[n] = size;
+            ++n;
+            left -= size;
+        }
+    }
+    return n;
+}
+
+}  // namespace wm

@@ -1,0 +1,70 @@
+// Internal objects of libwm and the launch sequences of a block and a step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "../../include/wm.h"
+#include "kernels.hpp"
+
+namespace wm {
+
+// Device pointers of one block's parameters (owned by the processor).
+struct BlockWeights {
+    const float *ln1_g, *ln1_b, *b_qkv, *rpb_log2, *b_o, *ln2_g, *ln2_b, *b_1, *b_2;
+    const void *w_qkv, *w_o, *w_1, *w_2;   // [out][in], processor precision
+};
+
+constexpr int MAX_BLOCKS = 64;
+
+// Kernel kinds of a block, in launch order (timing records).
+enum ProfKind : int { PK_LN1 = 0, PK_QKV, PK_NA, PK_PROJ, PK_LN2, PK_MLP1, PK_MLP2, PK_N };
+
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace wm
+
+struct wm_ctx {
+    int device = 0;
+    void *ws = nullptr;       // block intermediates, grown on demand
+    size_t ws_bytes = 0;
+    void *small = nullptr;    // 4 KiB of device scratch (reductions)
+    bool prof = false;        // bracket every block kernel with HIP events
+    std::vector<wm::ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+};
+
+struct wm_processor {
+    wm_grid g{};
+    int nb = 0, mlp = 4, device = 0;
+    wm_precision prec = WM_F32;
+    void *mem = nullptr;
+    size_t bytes = 0;
+    wm::BlockWeights blk[wm::MAX_BLOCKS];
+};
+
+namespace wm {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int ctx_reserve(wm_ctx *ctx, size_t bytes);
+
+// Bytes of workspace a block of processor p needs for B states.
+size_t block_workspace_bytes(const wm_processor *p, int B);
+int reserve_block_workspace(wm_ctx *ctx, const wm_processor *p, int B);
+// Timing records (no-ops unless ctx->prof).
+int prof_begin(wm_ctx *ctx, hipStream_t s, int kind);
+int prof_end(wm_ctx *ctx, hipStream_t s);
+// Enqueue one block / one step on `s` (workspace already reserved).
+int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s);
+int run_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, hipStream_t s);
+// Greedy 6 h / 1 h schedule; writes up to cap entries if out != nullptr and
+// returns the number of steps.
+int greedy_schedule(int lead_hours, int *out, int cap);
+
+}  // namespace wm

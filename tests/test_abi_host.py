@@ -1,0 +1,84 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load, export every function include/wm.h declares, and its
+host-only logic (the greedy schedule, argument validation) must match the
+oracle bit for bit.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for hdr in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not hdr.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", hdr)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(wm_[a-z0-9_]+)\s*\(",
+                             text, flags=re.M):
+            names.append(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def wm():
+    import paper_2503_22235_amd as wm
+    if not os.path.exists(wm.LIB_PATH):
+        from paper_2503_22235_amd import build
+        build.build()
+    wm.lib()
+    return wm
+
+
+def test_header_symbols_exported(wm):
+    names = _declared_functions()
+    assert len(names) >= 15
+    L = ctypes.CDLL(wm.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert "gfx950" in wm.wm_version()
+
+
+def test_schedule_matches_oracle_bit_exact(wm):
+    from oracle import wm_oracle as O
+    for lead in list(range(0, 400)) + [341, 1000, 5000]:
+        assert wm.wm_schedule(lead) == O.schedule(lead)
+
+
+def test_schedule_errors(wm):
+    L = wm.lib()
+    assert L.wm_schedule(-1, None, 0) == -1
+    assert b"negative" in L.wm_last_error()
+    buf = (ctypes.c_int * 2)()
+    assert L.wm_schedule(13, buf, 2) == -1          # needs 3 entries
+    assert L.wm_schedule(12, buf, 2) == 2 and list(buf) == [6, 6]
+
+
+def test_argument_validation_without_gpu(wm):
+    """Invalid windows, shapes and precisions are rejected before any GPU work."""
+    L = wm.lib()
+    bad = [
+        wm.wm_grid(8, 90, 180, 512, 16, 4, 7, 7, 4),     # even window
+        wm.wm_grid(4, 90, 180, 512, 16, 5, 7, 7, 4),     # window larger than axis
+        wm.wm_grid(8, 90, 180, 500, 16, 5, 7, 7, 4),     # head dim not 32
+        wm.wm_grid(8, 90, 180, 512, 16, 5, 7, 7, 9),     # bad periodic mask
+    ]
+    for g in bad:
+        assert L.wm_nat_indices(ctypes.byref(g), 1, None) == wm_status("WM_EINVAL")
+    assert L.wm_layernorm(4, 100, 1, 1, 1, 1e-5, 1, 1, None) == wm_status("WM_EINVAL")
+    assert L.wm_linear(4, 100, 64, 1, 1, 1, 1, 0, 1, None) == wm_status("WM_EINVAL")
+    assert L.wm_linear(4, 128, 64, 1, 1, 1, 1, 5, 1, None) == wm_status("WM_EINVAL")
+    assert L.wm_processor_block(None, None, 0, 1, None, None) == wm_status("WM_EINVAL")
+    assert L.wm_rollout(None, None, None, 1, None, 6, None) == wm_status("WM_EINVAL")
+
+
+def wm_status(name):
+    text = open(os.path.join(ROOT, "include", "wm.h")).read()
+    m = re.search(name + r"\s*=\s*(-?\d+)", text)
+    return int(m.group(1))

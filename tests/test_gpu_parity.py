@@ -1,0 +1,313 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative L2 over the compared values): window tables and
+schedules bit-exact; FP32 path <= 1e-5; BF16 path <= 1e-2.  BF16 inputs are
+rounded to bfloat16 first and the oracle gets the same rounded values.
+"""
+import numpy as np
+import pytest
+
+import wm_synth as S
+from oracle import wm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-5, 1: 1e-2}
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2503_22235_amd as wm
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    wm.lib()
+    ctx = wm.wm_ctx_create(0)
+    yield wm, torch, ctx
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def grid(Z, Y, X, C=128, heads=4, Kz=3, Ky=5, Kx=5, pm=0x4):
+    return S.Grid(Z=Z, Y=Y, X=X, C=C, heads=heads, Kz=Kz, Ky=Ky, Kx=Kx, periodic_mask=pm)
+
+
+SMALL_GRIDS = [
+    grid(5, 45, 90),                                  # the single-block case
+    grid(3, 7, 9, Kz=3, Ky=5, Kx=5),                  # ragged group tails
+    grid(8, 12, 20, Kz=5, Ky=7, Kx=7),                # full-size window on a small grid
+    grid(2, 5, 6, Kz=1, Ky=5, Kx=3, pm=0x5),          # periodic level axis, full lat
+    grid(3, 4, 5, Kz=3, Ky=3, Kx=5, pm=0x7),          # all periodic, full window
+    grid(1, 1, 1, Kz=1, Ky=1, Kx=1),                  # single token
+    grid(3, 10, 21, Kz=3, Ky=5, Kx=5),                # tiled kernel: level/lat/lon tails
+    grid(8, 16, 24, C=64, heads=2, Kz=5, Ky=7, Kx=7),  # tiled kernel, 5x7x7 window
+]
+
+
+# ---------------------------------------------------------------------------
+def test_nat_indices_bit_exact(env):
+    wm, torch, ctx = env
+    for g in SMALL_GRIDS + [S.CFG2, grid(40, 33, 17, Kz=39, Ky=1, Kx=17, pm=0x2)]:
+        say("indices", g)
+        n = g.Z + g.Y + g.X
+        out = torch.full((2 * n,), -7, dtype=torch.int32, device="cuda")
+        wm.wm_nat_indices(g, out)
+        got = out.cpu().numpy()
+        exp0, exp1 = [], []
+        for N, K, per in ((g.Z, g.Kz, g.periodic_mask & 1), (g.Y, g.Ky, g.periodic_mask & 2),
+                          (g.X, g.Kx, g.periodic_mask & 4)):
+            keys, off = O.window_axis(N, K, bool(per))
+            exp0 += list(keys[:, 0])
+            exp1 += list(off[:, 0] + K - 1)
+        assert np.array_equal(got[:n], np.array(exp0)), g
+        assert np.array_equal(got[n:], np.array(exp1)), g
+
+
+# ---------------------------------------------------------------------------
+def _bf16_round(torch, a):
+    return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float32).numpy()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_layernorm(env, prec):
+    wm, torch, ctx = env
+    r = np.random.default_rng(1)
+    for M, C in ((1000, 128), (777, 512), (5, 1024), (64, 256)):
+        say("layernorm", prec, M, C)
+        x = (r.standard_normal((M, C)) * 3 + 0.5).astype(np.float32)
+        gm = (1 + 0.1 * r.standard_normal(C)).astype(np.float32)
+        bt = (0.1 * r.standard_normal(C)).astype(np.float32)
+        dt = torch.float32 if prec == 0 else torch.bfloat16
+        out = torch.empty((M, C), dtype=dt, device="cuda")
+        wm.wm_layernorm(M, C, torch.from_numpy(x).cuda(), torch.from_numpy(gm).cuda(),
+                        torch.from_numpy(bt).cuda(), 1e-5, prec, out)
+        got = out.float().cpu().numpy()
+        ref = O.layer_norm(x, gm, bt)
+        tol = 2e-6 if prec == 0 else 4e-3
+        assert O.rel_l2(got, ref) < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("epi", [0, 1, 2])
+def test_linear(env, prec, epi):
+    wm, torch, ctx = env
+    r = np.random.default_rng(2 + epi)
+    for M, N, K in ((1000, 384, 128), (129, 128, 512), (64, 2048, 512), (300, 64, 64)):
+        say("linear", prec, epi, M, N, K)
+        a = r.standard_normal((M, K)).astype(np.float32)
+        w = (r.standard_normal((N, K)) / np.sqrt(K)).astype(np.float32)
+        b = (0.1 * r.standard_normal(N)).astype(np.float32)
+        if prec == 1:
+            a, w = _bf16_round(torch, a), _bf16_round(torch, w)
+        dt = torch.float32 if prec == 0 else torch.bfloat16
+        ad = torch.from_numpy(a).cuda().to(dt)
+        wd = torch.from_numpy(w).cuda().to(dt)
+        bd = torch.from_numpy(b).cuda()
+        ref = a.astype(np.float64) @ w.astype(np.float64).T + b
+        if epi == 2:
+            x0 = r.standard_normal((M, N)).astype(np.float32)
+            out = torch.from_numpy(x0).cuda()
+            ref = x0 + ref
+        else:
+            out = torch.empty((M, N), dtype=dt, device="cuda")
+            if epi == 1:
+                ref = O.gelu(ref)
+        wm.wm_linear(M, N, K, prec, ad, wd, bd, epi, out)
+        got = out.float().cpu().numpy()
+        tol = 1e-6 if prec == 0 else 5e-3
+        assert O.rel_l2(got, ref) < tol, (M, N, K)
+
+
+# ---------------------------------------------------------------------------
+def _nat_case(env, g, prec, B=1, seed=0, qscale=1.0):
+    wm, torch, ctx = env
+    r = np.random.default_rng(seed)
+    shape = (B, g.T, g.heads, 32)
+    q = (r.standard_normal(shape) * qscale).astype(np.float32)
+    k = (r.standard_normal(shape) * qscale).astype(np.float32)
+    v = r.standard_normal(shape).astype(np.float32)
+    rpb = r.standard_normal(g.rpb_shape).astype(np.float32)
+    if prec == 1:
+        q, k, v = (_bf16_round(torch, a) for a in (q, k, v))
+    dt = torch.float32 if prec == 0 else torch.bfloat16
+    dev = [torch.from_numpy(a).cuda().to(dt) for a in (q, k, v)]
+    out = torch.empty(shape, dtype=dt, device="cuda")
+    wm.wm_nat_forward(ctx, g, B, prec, dev[0], dev[1], dev[2], torch.from_numpy(rpb).cuda(), out)
+    got = out.float().cpu().numpy()
+    ref = np.stack([O.nat_c(q[b], k[b], v[b], rpb, g) for b in range(B)])
+    return got, ref
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nat_forward_small_grids(env, prec):
+    for i, g in enumerate(SMALL_GRIDS):
+        say("nat", prec, g)
+        got, ref = _nat_case(env, g, prec, B=2 if i == 1 else 1, seed=i, qscale=2.0)
+        err = O.rel_l2(got, ref)
+        say("  rel_l2", err)
+        assert err <= TOL[prec], (g, err)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nat_forward_full_size(env, prec):
+    """Attention alone at 8 x 90 x 180, 16 heads, window 5x7x7, every output."""
+    g = S.CFG2
+    say("nat full size", prec)
+    got, ref = _nat_case(env, g, prec, seed=11)
+    err = O.rel_l2(got, ref)
+    say("  rel_l2", err)
+    assert err <= TOL[prec]
+
+
+def test_nat_unit_window_is_v(env):
+    g = grid(3, 4, 6, Kz=1, Ky=1, Kx=1)
+    got, ref = _nat_case(env, g, 0, seed=9)
+    assert np.abs(got - ref).max() < 1e-6
+
+
+def test_nat_roll_lon_by_group_width(env):
+    """Rolling q, k, v by a whole query-group width in lon rolls the output
+    (bit-exact: every query sees the same keys in the same order)."""
+    wm, torch, ctx = env
+    g = grid(5, 45, 90)
+    r = np.random.default_rng(4)
+    shape = (1, g.Z, g.Y, g.X, g.heads, 32)
+    ten = [torch.from_numpy(r.standard_normal(shape).astype(np.float32)).cuda() for _ in range(3)]
+    rpb = torch.from_numpy(r.standard_normal(g.rpb_shape).astype(np.float32)).cuda()
+    outs = []
+    for s in (0, 2, 10):
+        rolled = [torch.roll(t, s, dims=3).contiguous() for t in ten]
+        out = torch.empty_like(rolled[0])
+        wm.wm_nat_forward(ctx, g, 1, 0, *rolled, rpb, out)
+        outs.append(torch.roll(out, -s, dims=3).cpu())
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 1])
+def test_block_small_config(env, prec):
+    """One processor block at 5 x 45 x 90, C=128, 4 heads, window 3x5x5."""
+    wm, torch, ctx = env
+    g = S.CFG1
+    x = S.latent_state(g, 1, 0)
+    params = S.processor_params(g, 1, 1)
+    say("block cfg1", prec)
+    p = wm.wm_processor_create(ctx, g, 1, 4, prec, params)
+    xd = torch.from_numpy(x).cuda()
+    wm.wm_processor_block(ctx, p, 0, 1, xd)
+    got = xd.cpu().numpy()
+    ref = O.block(x, S.split_block_params(g, params, 0), g)
+    err = O.rel_l2(got, ref)
+    inc = O.rel_l2(got - x, ref - x)
+    say(f"  rel_l2={err:.3e} increment rel_l2={inc:.3e}")
+    assert err <= TOL[prec]
+    assert inc <= (1e-4 if prec == 0 else 2e-2)
+    p.close()
+
+
+def test_block_identity_when_output_maps_zero(env):
+    wm, torch, ctx = env
+    g = grid(4, 9, 12)
+    params = S.processor_params(g, 1, 1)
+    blk = S.split_block_params(g, params, 0)
+    for name in ("w_o", "b_o", "w_2", "b_2"):
+        blk[name][...] = 0
+    x = S.latent_state(g, 1, 0)
+    for prec in (0, 1):
+        p = wm.wm_processor_create(ctx, g, 1, 4, prec, params)
+        xd = torch.from_numpy(x).cuda()
+        wm.wm_processor_block(ctx, p, 0, 1, xd)
+        assert np.array_equal(xd.cpu().numpy(), x)
+        p.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_step_small_config_and_batch_invariance(env, prec):
+    """An 8-block step at the small config; a batch of 2 states gives each
+    state exactly what it gets alone."""
+    wm, torch, ctx = env
+    g = S.CFG1
+    nb = 8
+    params = S.processor_params(g, nb, 1)
+    x = S.latent_state(g, 2, 0)
+    say("step cfg1", prec)
+    p = wm.wm_processor_create(ctx, g, nb, 4, prec, params)
+    xb = torch.from_numpy(x).cuda()
+    wm.wm_processor_step(ctx, p, 2, xb)
+    x0 = torch.from_numpy(x[:1].copy()).cuda()
+    wm.wm_processor_step(ctx, p, 1, x0)
+    assert torch.equal(xb[:1], x0)
+    blocks = [S.split_block_params(g, params, b) for b in range(nb)]
+    ref = O.processor_step(x[:1], blocks, g)
+    err = O.rel_l2(x0.cpu().numpy(), ref)
+    say(f"  step rel_l2={err:.3e}")
+    assert err <= TOL[prec] * (2 if prec == 1 else 4)
+    p.close()
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 1])
+def test_blocks_full_size_sampled(env, prec):
+    """Every block of an 8-block processor at 8 x 90 x 180, C=512, 16 heads,
+    window 5x7x7, on the same seeded state; outputs compared with the oracle
+    at about 600 sampled tokens (borders, poles and the lon seam included)."""
+    wm, torch, ctx = env
+    g = S.CFG2
+    nb = 8
+    params = S.processor_params(g, nb, 1)
+    x = S.latent_state(g, 1, 0)
+    r = np.random.default_rng(5)
+    tok = np.unique(np.concatenate([
+        r.choice(g.T, 400, replace=False),
+        np.arange(0, g.X, 3), np.arange(g.T - g.X, g.T, 3),    # pole rows
+        np.arange(0, g.T, 17 * g.X) + g.X - 1,                  # lon seam
+    ]))
+    p = wm.wm_processor_create(ctx, g, nb, 4, prec, params)
+    xd = torch.from_numpy(x).cuda()
+    for b in range(nb):
+        y = xd.clone()
+        say("block cfg2", prec, b)
+        wm.wm_processor_block(ctx, p, b, 1, y)
+        got = y.reshape(g.T, g.C)[torch.from_numpy(tok).cuda()].cpu().numpy()
+        ref = O.block_at(x[0], S.split_block_params(g, params, b), g, tok)
+        xs = x[0].reshape(g.T, g.C)[tok]
+        err, inc = O.rel_l2(got, ref), O.rel_l2(got - xs, ref - xs)
+        say(f"  rel_l2={err:.3e} increment={inc:.3e}")
+        assert err <= TOL[prec], (b, err)
+    p.close()
+
+
+# ---------------------------------------------------------------------------
+def test_rollout_small_config(env):
+    wm, torch, ctx = env
+    g = grid(4, 9, 12)
+    p6p = S.processor_params(g, 2, 1, proc=0)
+    p1p = S.processor_params(g, 2, 2, proc=1)
+    p6 = wm.wm_processor_create(ctx, g, 2, 4, 0, p6p)
+    p1 = wm.wm_processor_create(ctx, g, 2, 4, 0, p1p)
+    x = S.latent_state(g, 1, 0)
+    b6 = [S.split_block_params(g, p6p, b) for b in range(2)]
+    b1 = [S.split_block_params(g, p1p, b) for b in range(2)]
+    for lead in (0, 1, 6, 13):
+        say("rollout", lead)
+        xd = torch.from_numpy(x).cuda()
+        wm.wm_rollout(ctx, p6, p1, 1, xd, lead)
+        ref = O.rollout(x, b6, b1, g, lead)
+        if lead == 0:
+            assert np.array_equal(xd.cpu().numpy(), x)
+        else:
+            assert O.rel_l2(xd.cpu().numpy(), ref) <= 1e-5 * (1 + lead)
+    p6.close()
+    p1.close()
+
+
+def test_relerr_gpu_fp64(env):
+    wm, torch, ctx = env
+    r = np.random.default_rng(6)
+    ref = r.standard_normal(100003)
+    y = (ref + 1e-3 * r.standard_normal(ref.shape)).astype(np.float32)
+    got = wm.wm_relerr_l2(ctx, torch.from_numpy(y).cuda(), torch.from_numpy(ref).cuda())
+    assert abs(got - O.rel_l2(y, ref)) < 1e-12
