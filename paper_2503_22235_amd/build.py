@@ -21,6 +21,14 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 
 
+# Per-file extra flags.  The attention kernels never create NaNs (masked
+# scores are -inf, reference maxima start finite), so their max reductions
+# can skip IEEE NaN canonicalisation.
+EXTRA = {
+    "k_nat_tile.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"],
+}
+
+
 def sources():
     out = []
     for f in sorted(os.listdir(CSRC)):
@@ -32,7 +40,7 @@ def sources():
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     lang = ["-x", "hip"]
-    cmd = [HIPCC] + COMMON + lang + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + COMMON + EXTRA.get(os.path.basename(src), []) + lang + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -166,6 +166,8 @@ int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec, cons
     if (B == 0) return WM_OK;
     if (!q || !k || !v || !rpb || !out) return fail(WM_EINVAL, "NULL tensor");
     const long T = (long)g->Z * g->Y * g->X;
+    rc = ctx_reserve(ctx, (size_t)g->heads * NAT_TBL_WS_FLOATS * 4);
+    if (rc) return rc;
     NatArgs a{};
     a.q = q; a.k = k; a.v = v;
     a.bs = T * g->C; a.ts = g->C; a.hs = 32;
@@ -175,6 +177,7 @@ int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec, cons
     a.bscale = LOG2E;
     a.B = B; a.Z = g->Z; a.Y = g->Y; a.X = g->X; a.H = g->heads;
     a.Kz = g->Kz; a.Ky = g->Ky; a.Kx = g->Kx; a.periodic = g->periodic_mask;
+    a.tbl_ws = (float *)ctx->ws;
     hipError_t e = launch_nat(a, prec == WM_BF16, (hipStream_t)stream);
     return e == hipSuccess ? WM_OK : hip_fail(e, "nat launch");
 }

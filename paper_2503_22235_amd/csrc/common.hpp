@@ -59,6 +59,25 @@ __device__ __forceinline__ float wave_max(float v) {
     return v;
 }
 
+// GELU(z) = z * Phi(z) = z/2 * (1 + erf(z / sqrt 2)), with erf from the
+// rational approximation of Abramowitz & Stegun, Handbook of Mathematical
+// Functions, eq. 7.1.26 (Hastings): for x >= 0,
+//   erf(x) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-x^2),
+//   t = 1 / (1 + p x),  |error| <= 1.5e-7.
+__device__ __forceinline__ float gelu_as(float z) {
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+    float poly = fmaf(1.061405429f, t, -1.453152027f);
+    poly = fmaf(poly, t, 1.421413741f);
+    poly = fmaf(poly, t, -0.284496736f);
+    poly = fmaf(poly, t, 0.254829592f);
+    poly *= t;
+    const float ex = __builtin_amdgcn_exp2f(-x * x * LOG2E);
+    float erfx = fmaf(-poly, ex, 1.0f);
+    erfx = z < 0.f ? -erfx : erfx;
+    return 0.5f * z * (1.0f + erfx);
+}
+
 // ---------------------------------------------------------------------------
 // Neighborhood windows (WeatherMesh-3 Sec. 2.1 NATTEN; App. A.2).  One axis
 // of length n with odd window k, r = (k-1)/2.

@@ -24,10 +24,6 @@ constexpr int NT = 256;
 
 __device__ __forceinline__ int swz(int row) { return (row >> 1) & 7; }
 
-__device__ __forceinline__ float gelu_erf(float z) {
-    return 0.5f * z * (1.0f + erff(z * 0.70710678118654752440f));
-}
-
 __device__ __forceinline__ void store4(float *p, f32x4 v) {
     *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]);
 }
@@ -52,7 +48,7 @@ __device__ __forceinline__ void epilogue4(const EpiArgs &ep, int M, int N, int m
         TO *dst = (TO *)ep.out + (((size_t)(part * ep.H + h) * M + m) * 32 + e);
         store4(dst, v);
     } else if constexpr (EPI == EPI_GELU) {
-        v[0] = gelu_erf(v[0]); v[1] = gelu_erf(v[1]); v[2] = gelu_erf(v[2]); v[3] = gelu_erf(v[3]);
+        v[0] = gelu_as(v[0]); v[1] = gelu_as(v[1]); v[2] = gelu_as(v[2]); v[3] = gelu_as(v[3]);
         store4((TO *)ep.out + (size_t)m * N + n, v);
     } else if constexpr (EPI == EPI_RESID) {
         float *r = ep.resid + (size_t)m * N + n;
@@ -221,6 +217,7 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
 hipError_t launch_gemm(const void *A, const void *W, int M, int N, int K, bool a_bf16, EpiKind epi,
                        const EpiArgs &ep, hipStream_t stream) {
     if (M <= 0) return hipSuccess;
+    if (a_bf16 && gemm_lds_applies(M, N, K)) return launch_gemm_lds(A, W, M, N, K, epi, ep, stream);
     if (a_bf16) {
         if (N % 128 == 0) return launch_cfg<bf16, 128, 128>(A, W, M, N, K, epi, ep, stream);
         return launch_cfg<bf16, 128, 64>(A, W, M, N, K, epi, ep, stream);

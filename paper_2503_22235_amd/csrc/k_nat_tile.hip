@@ -3,27 +3,32 @@
 //
 // Workgroup = 256 threads, one head, a query tile of 4 levels x 4 lats x
 // 8 lons (128 queries = 8 groups of 4x2x2).  The union of the tile's
-// windows (the halo: <= 6 x 10 x 14 tokens at 8 levels and a 5x7x7 window)
-// is staged once in LDS -- K row-major with 16-byte chunks swizzled, V
-// transposed (d-major) -- and shared by all 8 query groups.  Each wave owns
-// two groups with the same level/lat window pattern, so they share the
-// relative-position-bias lookups.
+// windows (the halo: 6 x 10 x 14 tokens at 8 levels with a 5x7x7 window)
+// of V is staged once in LDS, transposed (d-major, row stride padded so the
+// transposing writes hit distinct banks), and shared by all 8 query groups.
+// K fragments are read straight from global memory (buffer loads, one chunk
+// ahead; the tile's groups re-read them from L1/L2), which keeps the LDS
+// footprint at ~66 KB so two workgroups share a CU and one's loads overlap
+// the other's math.  Each wave owns two groups with the same level/lat
+// window pattern, so they share the relative-position-bias lookups, which
+// come from a per-head table prepared once per launch (nat_bias_prep).
 //
 // Per group the halo is walked in chunks of 32 keys = 4 lat rows x 8 lon
 // columns at one level.  A chunk costs 5 MFMA:
 //   S^T = K . Q^T + B        2 x 16x16x32 (the bias-and-mask tile B is the
 //                            accumulator input: masked keys enter as -inf)
 //   O^T += V^T . P^T         2 x 16x16x32
-//   l   += 1 . P^T           1 x 16x16x32 (row sums of the bf16 weights)
-// The softmax runs in base 2 with a lazily updated reference maximum:
-// the weights are exp2(s - m_ref) and m_ref (with the accumulators) is only
-// moved when a chunk's maximum exceeds it by more than 8, so the weights
-// stay <= 256 and most chunks need no rescaling.  Max and sums are float32.
+//   l   += 1 . P^T           1 x 16x16x32 (sums of the bf16 weights)
+// The softmax runs in base 2 with a lazily moved reference maximum: the
+// weights are exp2(s - m_ref), and m_ref (with the accumulators) is only
+// moved when a chunk's maximum exceeds it by more than 8, so weights stay
+// <= 256 and most chunks need no rescaling.  Max and sums are float32.
 //
 // Layout facts used (lane l, g = l/16, r = l%16) for the gfx950 bf16 MFMA
 // 16x16x32: A[r][8g..8g+7], B[8g..8g+7][r], D[4g..4g+3][r].  A lane's
 // scores in a chunk are keys {4g+i, 16+4g+i}; the P.V contraction takes its
-// k index in that order (k-slot 8g + 4j + i <-> key 16j + 4g + i).
+// k index in that order (k-slot 8g + 4j + i <-> key 16j + 4g + i).  The
+// query max is shared by lanes l, l^16, l^32, l^48: two permlane swaps.
 #include <algorithm>
 #include <cmath>
 
@@ -37,8 +42,7 @@ constexpr int GX = 2;                     // group lon extent
 constexpr int XW = 16;                    // halo lon extent, padded (>= TX + Kx - 1)
 constexpr int XT = 9;                     // bias table lon extent: hx - xq_rel + 1
 constexpr float TAU = 8.0f;               // lazy rescale threshold (log2 units)
-
-__device__ __forceinline__ int kswz(int row, int x) { return ((x >> 2) ^ row) & 3; }
+constexpr int LD_BATCH = 4;               // halo items loaded before they are stored
 
 __device__ __forceinline__ void clamp_range(int a0, int tsize, int N, int K, int &lo, int &n) {
     const int last = min(a0 + tsize - 1, N - 1);
@@ -46,24 +50,64 @@ __device__ __forceinline__ void clamp_range(int a0, int tsize, int N, int K, int
     n = win_start(last, N, K, false) + K - lo;
 }
 
+// The workgroup's base pointer, held in scalar registers (it is uniform;
+// saying so lets buffer loads take it as a scalar resource).
+__device__ __forceinline__ void *uniform_ptr(const void *p) {
+    const unsigned long long v = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return (void *)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float xmax16_32(float v) {
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+
 // QSCALED: q already carries the factor log2(e)/sqrt(d) (the block path folds
 // it into the QKV projection); otherwise scores are scaled after the MFMA and
-// the bias table is stored divided by the scale.
+// the bias table is stored divided by that scale.
+template <int KZ, int KY, int KX>
+constexpr int tbl_padded() { return ((2 * KZ - 1) * (2 * KY - 1) * XT + 4 + 3) & ~3; }
+
+// Per-head bias table in the layout the tile kernel reads: tbl[iz][iy][ixt]
+// (ixt = key lon slot - query lon slot + 1), lon validity folded in as
+// -inf, followed by 4 entries of -inf that masked (level, lat) rows read.
 template <int KZ, int KY, int KX, bool QSCALED>
-__global__ __launch_bounds__(256, 1) void nat_tile_kernel(NatArgs p, int ZWmax, int YWmax) {
+__global__ void nat_bias_prep(NatArgs p) {
+    constexpr int RX = (KX - 1) / 2, BY = 2 * KY - 1, BZ = 2 * KZ - 1;
+    constexpr int TBL = BZ * BY * XT, TBLP = tbl_padded<KZ, KY, KX>();
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= p.H * TBLP) return;
+    const int h = e / TBLP, i = e - h * TBLP;
+    const float bs = QSCALED ? p.bscale : p.bscale / p.qscale;
+    float v = -INFINITY;
+    if (i < TBL) {
+        const int ixt = i % XT, rest = i / XT;
+        const int dx = ixt - 1 - RX;
+        if (dx >= -RX && dx <= RX) v = p.rpb[((size_t)h * BZ * BY + rest) * (2 * KX - 1) + dx + KX - 1] * bs;
+    }
+    p.tbl_ws[e] = v;
+}
+
+template <int KZ, int KY, int KX, bool QSCALED>
+__global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, int YWmax) {
     constexpr int RX = (KX - 1) / 2;
     constexpr int BY = 2 * KY - 1;
     constexpr int BZ = 2 * KZ - 1;
     constexpr int NCH = 2 * (4 + KZ - 1);           // max chunks per group
     constexpr int TBL = BZ * BY * XT;               // bias table entries
-    static_assert(2 + KX - 1 <= 8 && 2 + KY - 1 <= 8, "window too large for 8-wide group halo");
+    static_assert(2 + KX - 1 <= 8 && 2 + KY - 1 <= 8, "window too large for the 8-wide group halo");
+    static_assert(NCH <= 16, "chunk mask is 32 bits");
 
+    constexpr int TBLP = tbl_padded<KZ, KY, KX>();
     extern __shared__ __align__(16) unsigned char smem[];
-    float *tbl = (float *)smem;                                  // [BZ][BY][XT] + 4 of -inf
-    const int tbl_bytes = ((TBL + 4) * 4 + 15) & ~15;
+    float *tbl = (float *)smem;                                  // [BZ][BY][XT] + 4 x -inf
     const int nslot_max = ZWmax * YWmax * XW;
-    uint4 *Ks = (uint4 *)(smem + tbl_bytes);                     // [slot][4 chunks]
-    unsigned short *Vt = (unsigned short *)(smem + tbl_bytes + nslot_max * 64);  // [32][nslot]
+    const int VS = nslot_max + 4;                                // Vt row stride (elements)
+    unsigned char *Vtb = smem + TBLP * 4;                        // [32][VS] bf16
 
     // ---- tile of this workgroup (XCD-aware order over (b, h, tile)) ----
     const int ntz = (p.Z + TZ - 1) / TZ, nty = (p.Y + TY - 1) / TY, ntx = (p.X + TX - 1) / TX;
@@ -92,36 +136,51 @@ __global__ __launch_bounds__(256, 1) void nat_tile_kernel(NatArgs p, int ZWmax, 
     const bf16 *qb = (const bf16 *)p.q + (size_t)b * p.bs + (size_t)h * p.hs;
     const int tid = threadIdx.x;
 
-    // ---- bias table: tbl[iz][iy][ixt], lon validity folded in ----
+    // ---- bias table of this head (prepared by nat_bias_prep) ----
     {
-        const float *r = p.rpb + (size_t)h * BZ * BY * (2 * KX - 1);
-        const float bs = QSCALED ? p.bscale : p.bscale / p.qscale;
-        for (int e = tid; e < TBL + 4; e += 256) {
-            float v = -INFINITY;
-            if (e < TBL) {
-                const int ixt = e % XT, rest = e / XT;
-                const int dx = ixt - 1 - RX;              // hx - xq_rel - r
-                if (dx >= -RX && dx <= RX) v = r[rest * (2 * KX - 1) + dx + KX - 1] * bs;
-            }
-            tbl[e] = v;
-        }
+        const uint4 *src = (const uint4 *)(p.tbl_ws + (size_t)h * TBLP);
+        for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
     }
-    // ---- K and V halo: slot = (hz * yn + hy) * XW + hx ----
-    for (int e = tid; e < nslot * 4; e += 256) {
-        const int slot = e >> 2, c = e & 3;
-        const int hx = slot % XW, row = slot / XW;
-        const int hy = row % yn, hz = row / yn;
-        int xx = (xlo + (hx < TX + KX - 1 ? hx : 0)) % p.X;
-        xx = xx < 0 ? xx + p.X : xx;
-        const long tok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X + xx;
-        const uint4 kv = *(const uint4 *)(kb + tok * p.ts + 8 * c);
-        Ks[slot * 4 + (c ^ kswz(row, hx))] = kv;
-        const uint4 vv = *(const uint4 *)(vb + tok * p.ts + 8 * c);
-        const unsigned w[4] = {vv.x, vv.y, vv.z, vv.w};
+    // ---- V halo, transposed.  Item = (slot pair, 16-byte chunk c), c
+    // fastest: 4 lanes read the 2 x 64 contiguous bytes of two neighbouring
+    // tokens.  Loads of a batch are issued before any store (items past the
+    // end reload the last item and are not stored).
+    {
+        const int nitems = nslot * 2;
+        unsigned *Vt32 = (unsigned *)Vtb;
+        for (int e0 = tid; e0 < nitems; e0 += 256 * LD_BATCH) {
+            uint4 v0[LD_BATCH], v1[LD_BATCH];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            Vt[(8 * c + 2 * q) * nslot + slot] = (unsigned short)(w[q] & 0xffffu);
-            Vt[(8 * c + 2 * q + 1) * nslot + slot] = (unsigned short)(w[q] >> 16);
+            for (int u = 0; u < LD_BATCH; ++u) {
+                const int e = min(e0 + 256 * u, nitems - 1);
+                const int pr = e >> 2, c = e & 3;
+                const int slot = 2 * pr;                  // even: both slots share the row
+                const int hx = slot % XW, row = slot / XW;
+                const int hy = row % yn, hz = row / yn;
+                int x0c = xlo + (hx < TX + KX - 1 ? hx : 0);
+                int x1c = xlo + (hx + 1 < TX + KX - 1 ? hx + 1 : 0);
+                x0c = x0c < 0 ? x0c + p.X : (x0c >= p.X ? x0c - p.X : x0c);
+                x1c = x1c < 0 ? x1c + p.X : (x1c >= p.X ? x1c - p.X : x1c);
+                const long rtok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X;
+                v0[u] = *(const uint4 *)(vb + (size_t)(rtok + x0c) * p.ts + 8 * c);
+                v1[u] = *(const uint4 *)(vb + (size_t)(rtok + x1c) * p.ts + 8 * c);
+            }
+#pragma unroll
+            for (int u = 0; u < LD_BATCH; ++u) {
+                const int e = e0 + 256 * u;
+                if (e < nitems) {
+                    const int pr = e >> 2, c = e & 3;
+                    unsigned *vrow = Vt32 + (8 * c) * (VS >> 1) + pr;
+                    vrow[0 * (VS >> 1)] = (v0[u].x & 0xffffu) | (v1[u].x << 16);
+                    vrow[1 * (VS >> 1)] = (v0[u].x >> 16) | (v1[u].x & 0xffff0000u);
+                    vrow[2 * (VS >> 1)] = (v0[u].y & 0xffffu) | (v1[u].y << 16);
+                    vrow[3 * (VS >> 1)] = (v0[u].y >> 16) | (v1[u].y & 0xffff0000u);
+                    vrow[4 * (VS >> 1)] = (v0[u].z & 0xffffu) | (v1[u].z << 16);
+                    vrow[5 * (VS >> 1)] = (v0[u].z >> 16) | (v1[u].z & 0xffff0000u);
+                    vrow[6 * (VS >> 1)] = (v0[u].w & 0xffffu) | (v1[u].w << 16);
+                    vrow[7 * (VS >> 1)] = (v0[u].w >> 16) | (v1[u].w & 0xffff0000u);
+                }
+            }
         }
     }
     __syncthreads();
@@ -135,18 +194,17 @@ __global__ __launch_bounds__(256, 1) void nat_tile_kernel(NatArgs p, int ZWmax, 
     const int xrel = r16 & 1;
     const int zc = min(zq, p.Z - 1), yc = min(yq, p.Y - 1);
 
-    int zlg, zng, ylg, yng;
-    clamp_range(z0, 4, p.Z, KZ, zlg, zng);
+    int ylg, yng;
     clamp_range(min(y0g, p.Y - 1), 2, p.Y, KY, ylg, yng);
-    const int nch = 2 * zng;
-    const int dz = zlg - zlo, dy = ylg - ylo;
-    const int wz = win_start(zc, p.Z, KZ, false) - zlg;
+    const int nch = 2 * zn;                      // the group spans the tile's 4 levels
+    const int dy = ylg - ylo;
+    const int wz = win_start(zc, p.Z, KZ, false) - zlo;
     const int wy = win_start(yc, p.Y, KY, false) - ylg;
-    const int zb = zlg - zc + KZ - 1;
+    const int zb = zlo - zc + KZ - 1;
     const int yb = ylg - yc + KY - 1;
 
-    // validity of (level row hz, lat row hy) for this lane's query
-    unsigned vmask = 0;     // bit 2c + j
+    // validity of (level row, lat row) for this lane's query: bit 2c + j
+    unsigned vmask = 0;
 #pragma unroll
     for (int c = 0; c < NCH; ++c)
 #pragma unroll
@@ -157,15 +215,28 @@ __global__ __launch_bounds__(256, 1) void nat_tile_kernel(NatArgs p, int ZWmax, 
         }
     const int tb_lane = (zb * BY + yb + (g >> 1)) * XT + 4 * (g & 1) - xrel + 1;
 
-    // lat rows (clamped into the halo) for the K operand and the V operand
-    int krow[4], vrow[4];
+    // Lane-constant byte offsets of the K operand (key 16j + r16 of a chunk;
+    // global memory, within level zlo) and of the V^T operand (keys
+    // 16j + 4g + i; LDS, within level slab 0), for q = 2 * (c & 1) + j and
+    // the wave's two groups G.
+    const __amdgpu_buffer_rsrc_t krs = __builtin_amdgcn_make_buffer_rsrc(
+        uniform_ptr(kb), 0, 0x7ffffffe, 0x00020000);
+    const int tsb = (int)p.ts * 2;                          // token stride, bytes
+    int kofs[4][2], vofs[4][2];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int hy_k = 4 * (q >> 1) + 2 * (q & 1) + (r16 >> 3);
-        const int hy_v = 4 * (q >> 1) + 2 * (q & 1) + (g >> 1);
-        krow[q] = min(hy_k + dy, yn - 1);
-        vrow[q] = min(hy_v + dy, yn - 1);
+        const int hyk = min(4 * (q >> 1) + 2 * (q & 1) + (r16 >> 3) + dy, yn - 1);
+        const int hyv = min(4 * (q >> 1) + 2 * (q & 1) + (g >> 1) + dy, yn - 1);
+#pragma unroll
+        for (int G = 0; G < 2; ++G) {
+            const int xg = GX * (gxa + G);
+            int xk = xlo + (r16 & 7) + xg;
+            xk = xk < 0 ? xk + p.X : (xk >= p.X ? xk - p.X : xk);
+            kofs[q][G] = (((zlo * p.Y) + ylo + hyk) * p.X + xk) * tsb + 16 * g;
+            vofs[q][G] = (r16 * VS + hyv * XW + 4 * (g & 1) + xg) * 2;
+        }
     }
+    const int kslab = p.Y * p.X * tsb, vslab = yn * XW * 2;
 
     // Q fragments of the two groups
     bf16x8 qf[2];
@@ -191,76 +262,99 @@ __global__ __launch_bounds__(256, 1) void nat_tile_kernel(NatArgs p, int ZWmax, 
 #pragma unroll
     for (int e = 0; e < 8; ++e) ones[e] = __builtin_bit_cast(bf16, (unsigned short)0x3f80);
 
+    // K fragments ping-pong between two register sets: chunk c uses
+    // kreg[c & 1] while chunk c + 1 is in flight into the other.
+    bf16x8 kreg[2][2][2];
+#pragma unroll
+    for (int G = 0; G < 2; ++G)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            kreg[0][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(krs, kofs[j][G], 0, 0));
+
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-        if (c >= nch) break;
-        const int hz = (c >> 1) + dz;
-        // bias + mask tile (shared by both groups)
-        f32x4 binit[2];
+        if (c < nch) {
+            const int hz = c >> 1;
+            const unsigned char *Vz = Vtb + hz * vslab;
+            if (c + 1 < nch) {
+                const int cn = c + 1;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const bool ok = (vmask >> (2 * c + j)) & 1u;
-            const int a = ok ? tb_lane + (c >> 1) * BY * XT + (4 * (c & 1) + 2 * j) * XT : TBL;
+                for (int G = 0; G < 2; ++G)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) binit[j][i] = tbl[a + i];
-        }
-        bf16x8 pb[2];
-#pragma unroll
-        for (int G = 0; G < 2; ++G) {
-            const int xg = GX * (gxa + G);          // group lon offset in the halo
-            f32x4 s[2];
+                    for (int j = 0; j < 2; ++j)
+                        kreg[cn & 1][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
+                            krs, kofs[2 * (cn & 1) + j][G], (cn >> 1) * kslab, 0));
+            }
+            // bias + mask tile (shared by both groups)
+            f32x4 binit[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const int row = hz * yn + krow[(c & 1) * 2 + j];
-                const int hx = (r16 & 7) + xg;
-                const int slot = row * XW + hx;
-                const bf16x8 kf = __builtin_bit_cast(bf16x8, Ks[slot * 4 + (g ^ kswz(row, hx))]);
-                s[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf[G], binit[j], 0, 0, 0);
-                if constexpr (!QSCALED) {
+                const bool ok = (vmask >> (2 * c + j)) & 1u;
+                const int a = ok ? tb_lane + hz * BY * XT + (4 * (c & 1) + 2 * j) * XT : TBL;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) s[j][i] *= p.qscale;
-                }
+                for (int i = 0; i < 4; ++i) binit[j][i] = tbl[a + i];
             }
-            float cm = fmaxf(fmaxf(fmaxf(s[0][0], s[0][1]), fmaxf(s[0][2], s[0][3])),
-                             fmaxf(fmaxf(s[1][0], s[1][1]), fmaxf(s[1][2], s[1][3])));
-            cm = fmaxf(cm, __shfl_xor(cm, 16, 64));
-            cm = fmaxf(cm, __shfl_xor(cm, 32, 64));
-            if (__builtin_amdgcn_ballot_w64(cm > mref[G] + TAU)) {
-                const float mn = fmaxf(mref[G], cm);
-                const float al = exp2f(mref[G] - mn);
-                mref[G] = mn;
+            // scores of both groups
+            f32x4 s[2][2];
+            float cm[2];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    oacc[G][0][i] *= al;
-                    oacc[G][1][i] *= al;
-                    lacc[G][i] *= al;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) pb[G][4 * j + i] = (bf16)exp2f(s[j][i] - mref[G]);
-        }
-#pragma unroll
-        for (int G = 0; G < 2; ++G) {
-            const int xg = GX * (gxa + G);
-#pragma unroll
-            for (int tt = 0; tt < 2; ++tt) {
-                const unsigned short *vrowp = Vt + (16 * tt + r16) * nslot;
-                bf16x8 vf;
+            for (int G = 0; G < 2; ++G)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    const int slot = (hz * yn + vrow[(c & 1) * 2 + j]) * XW + 4 * (g & 1) + xg;
-                    const unsigned w0 = *(const unsigned *)(vrowp + slot);
-                    const unsigned w1 = *(const unsigned *)(vrowp + slot + 2);
-                    vf[4 * j + 0] = __builtin_bit_cast(bf16, (unsigned short)(w0 & 0xffffu));
-                    vf[4 * j + 1] = __builtin_bit_cast(bf16, (unsigned short)(w0 >> 16));
-                    vf[4 * j + 2] = __builtin_bit_cast(bf16, (unsigned short)(w1 & 0xffffu));
-                    vf[4 * j + 3] = __builtin_bit_cast(bf16, (unsigned short)(w1 >> 16));
+                    s[G][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kreg[c & 1][G][j], qf[G], binit[j], 0, 0, 0);
+                    if constexpr (!QSCALED) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) s[G][j][i] *= p.qscale;
+                    }
                 }
-                oacc[G][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb[G], oacc[G][tt], 0, 0, 0);
+#pragma unroll
+            for (int G = 0; G < 2; ++G) {
+                cm[G] = fmaxf(fmaxf(fmaxf(s[G][0][0], s[G][0][1]), fmaxf(s[G][0][2], s[G][0][3])),
+                              fmaxf(fmaxf(s[G][1][0], s[G][1][1]), fmaxf(s[G][1][2], s[G][1][3])));
+                cm[G] = xmax16_32(cm[G]);
             }
-            lacc[G] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, pb[G], lacc[G], 0, 0, 0);
+            // move the reference maxima only when a chunk exceeds them by TAU
+            if (__builtin_amdgcn_ballot_w64(cm[0] > mref[0] + TAU || cm[1] > mref[1] + TAU)) {
+#pragma unroll
+                for (int G = 0; G < 2; ++G) {
+                    const float mn = fmaxf(mref[G], cm[G]);
+                    const float al = __builtin_amdgcn_exp2f(mref[G] - mn);
+                    mref[G] = mn;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        oacc[G][0][i] *= al;
+                        oacc[G][1][i] *= al;
+                        lacc[G][i] *= al;
+                    }
+                }
+            }
+            bf16x8 pb[2];
+#pragma unroll
+            for (int G = 0; G < 2; ++G)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        pb[G][4 * j + i] = (bf16)__builtin_amdgcn_exp2f(s[G][j][i] - mref[G]);
+#pragma unroll
+            for (int G = 0; G < 2; ++G) {
+#pragma unroll
+                for (int tt = 0; tt < 2; ++tt) {
+                    bf16x8 vf;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const unsigned char *vp = Vz + vofs[2 * (c & 1) + j][G] + tt * 16 * VS * 2;
+                        const unsigned w0 = *(const unsigned *)vp;
+                        const unsigned w1 = *(const unsigned *)(vp + 4);
+                        vf[4 * j + 0] = __builtin_bit_cast(bf16, (unsigned short)(w0 & 0xffffu));
+                        vf[4 * j + 1] = __builtin_bit_cast(bf16, (unsigned short)(w0 >> 16));
+                        vf[4 * j + 2] = __builtin_bit_cast(bf16, (unsigned short)(w1 & 0xffffu));
+                        vf[4 * j + 3] = __builtin_bit_cast(bf16, (unsigned short)(w1 >> 16));
+                    }
+                    oacc[G][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb[G], oacc[G][tt], 0, 0, 0);
+                }
+                lacc[G] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, pb[G], lacc[G], 0, 0, 0);
+            }
         }
     }
 
@@ -292,8 +386,9 @@ int max_halo(int N, int K, int tsize) {
 }
 
 size_t tile_lds(int Kz, int Ky, int zw, int yw) {
-    const int tbl = (2 * Kz - 1) * (2 * Ky - 1) * XT;
-    return (((tbl + 4) * 4 + 15) & ~15) + (size_t)zw * yw * XW * 128;
+    const int tblp = (((2 * Kz - 1) * (2 * Ky - 1) * XT + 4 + 3) & ~3);
+    const size_t nslot = (size_t)zw * yw * XW;
+    return (size_t)tblp * 4 + 32 * (nslot + 4) * 2;
 }
 
 template <int KZ, int KY, int KX, bool QSCALED>
@@ -307,6 +402,8 @@ hipError_t launch_tile_q(const NatArgs &a, hipStream_t stream) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
+    constexpr int TBLP = tbl_padded<KZ, KY, KX>();
+    nat_bias_prep<KZ, KY, KX, QSCALED><<<(a.H * TBLP + 255) / 256, 256, 0, stream>>>(a);
     const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
     const long total = (long)ntiles * a.H * a.B;
     const unsigned grid = (unsigned)(((total + 7) >> 3) << 3);
@@ -328,7 +425,9 @@ size_t nat_tile_lds_bytes(const NatArgs &a) {
                        (a.Kz == 3 && a.Ky == 3 && a.Kx == 3);
     if (!known) return 0;
     if (a.X < TX + a.Kx - 1) return 0;     // the lon halo must not wrap onto itself
-    if ((long)a.Z * a.Y * a.X * a.B > (1L << 30)) return 0;
+    if (!a.tbl_ws) return 0;
+    // K is addressed with 32-bit byte offsets from the state's base
+    if ((long)a.Z * a.Y * a.X * a.ts * 2 >= (1L << 31)) return 0;
     return tile_lds(a.Kz, a.Ky, max_halo(a.Z, a.Kz, TZ), max_halo(a.Y, a.Ky, TY));
 }
 

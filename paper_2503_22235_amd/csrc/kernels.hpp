@@ -36,6 +36,11 @@ struct EpiArgs {
 hipError_t launch_gemm(const void *A, const void *W, int M, int N, int K, bool a_bf16,
                        EpiKind epi, const EpiArgs &ep, hipStream_t stream);
 
+// The 256x128 LDS-ring bf16 kernel (taken by launch_gemm when it applies).
+bool gemm_lds_applies(int M, int N, int K);
+hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, EpiKind epi,
+                           const EpiArgs &ep, hipStream_t stream);
+
 // --- 3-D neighborhood attention ------------------------------------------
 struct NatArgs {
     const void *q, *k, *v;  // element (b,t,h,e) at base + b*bs + t*ts + h*hs + e
@@ -48,7 +53,9 @@ struct NatArgs {
     int B, Z, Y, X, H;
     int Kz, Ky, Kx;
     unsigned periodic;
+    float *tbl_ws;          // device scratch of NAT_TBL_WS_FLOATS * H floats (tiled kernel)
 };
+constexpr int NAT_TBL_WS_FLOATS = 2048;     // per head, >= padded bias table
 // Picks the LDS-tiled bf16 kernel when it applies, else the generic one.
 hipError_t launch_nat(const NatArgs &a, bool bf16, hipStream_t stream);
 hipError_t launch_nat_generic(const NatArgs &a, bool bf16, hipStream_t stream);

@@ -10,7 +10,9 @@ size_t block_workspace_bytes(const wm_processor *p, int B) {
     const size_t C = p->g.C, F = C * p->mlp;
     const size_t esz = p->prec == WM_BF16 ? 2 : 4;
     const size_t big = (3 * C > F ? 3 * C : F);
-    return M * (C + big) * esz + 512;
+    const size_t act = (M * C * esz + 255) & ~(size_t)255;
+    const size_t bigb = (M * big * esz + 255) & ~(size_t)255;
+    return act + bigb + (size_t)p->g.heads * NAT_TBL_WS_FLOATS * 4;
 }
 
 int reserve_block_workspace(wm_ctx *ctx, const wm_processor *p, int B) {
@@ -59,6 +61,8 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     const size_t esz = bf ? 2 : 4;
     char *act = (char *)ctx->ws;
     char *big = act + (((size_t)M * C * esz + 255) & ~(size_t)255);
+    const size_t F3 = (size_t)(3 * C > F ? 3 * C : F);
+    float *tbl_ws = (float *)(big + (((size_t)M * F3 * esz + 255) & ~(size_t)255));
     hipError_t e;
 
     int rc;
@@ -91,6 +95,7 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     na.bscale = 1.0f;
     na.B = B; na.Z = g.Z; na.Y = g.Y; na.X = g.X; na.H = H;
     na.Kz = g.Kz; na.Ky = g.Ky; na.Kx = g.Kx; na.periodic = g.periodic_mask;
+    na.tbl_ws = tbl_ws;
     WM_TIMED(PK_NA, launch_nat(na, bf, s), "NA")
 
     EpiArgs er{};
