@@ -175,6 +175,52 @@ int wm_schedule(int lead_hours, int *steps_out, int cap);
 int wm_rollout(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
                int B, float *x, int lead_hours, void *stream);
 
+/* ---- Serving: a continuous-batching forecast loop -----------------------
+ * WeatherMesh-3 runs operationally, answering forecasts of any integer lead
+ * time from one latent state (Sec. 2.1; Sec. 3).  A server owns a scheduler
+ * thread.  Submitted requests wait in a FIFO until a state slot in HBM is
+ * free (slots are sized from the memory budget); their state is copied in
+ * on a copy stream while other requests compute.  Every scheduler iteration
+ * batches up to max_batch admitted requests whose next processor (six-hour
+ * or one-hour, greedy schedule) is the same into one step launch; requests
+ * join and leave the batch between steps.  Finished states are copied out
+ * on the copy stream.  Each request's result does not depend on what it
+ * was batched with (every kernel computes a state's tokens the same way
+ * whatever the batch).  Calls are thread-safe. */
+typedef struct {
+    int max_batch;             /* states per step launch (1..64)                  */
+    int state_bf16;            /* 1: slots hold bfloat16 states between steps      */
+    size_t hbm_budget_bytes;   /* slot memory cap; 0 = 3/4 of the free HBM         */
+    int max_slots;             /* 0 = as many as the budget allows (<= 1024)        */
+} wm_serve_cfg;
+
+typedef struct {
+    uint64_t id;
+    int lead_hours;
+    int steps;                 /* processor steps the request ran                  */
+    int batches;               /* step launches it was part of                     */
+    double t_submit, t_admit, t_done;   /* seconds on the steady clock            */
+} wm_req_stats;
+
+/* p6, p1 must share one grid and stay alive until wm_serve_destroy.  The
+ * server takes its own streams and workspace on ctx's device. */
+int wm_serve_create(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
+                    const wm_serve_cfg *cfg, wm_server **out);
+/* Queue a forecast of lead_hours >= 0 from HOST float32 x0 [Z][Y][X][C];
+ * x0 is copied before return.  Never waits for the GPU. */
+int wm_serve_submit(wm_server *s, const float *x0_host, int lead_hours,
+                    uint64_t *id_out);
+/* WM_OK: request id finished; its state is copied to HOST out_host (float32
+ * [Z][Y][X][C], may be NULL) and stats to *st (may be NULL), and the request
+ * is forgotten.  WM_EAGAIN: still queued or running.  WM_ENOTFOUND: unknown
+ * (or already collected) id.  Never waits for the GPU. */
+int wm_serve_poll(wm_server *s, uint64_t id, float *out_host, wm_req_stats *st);
+/* Counters: queued, admitted-and-running, finished-not-collected, slots. */
+int wm_serve_status(wm_server *s, int *queued, int *running, int *done, int *slots);
+/* Stops the scheduler (queued and running requests are dropped) and frees
+ * the server's memory. */
+void wm_serve_destroy(wm_server *s);
+
 /* Relative L2 error ||y - y_ref|| / ||y_ref|| of n values, accumulated in
  * float64 on the GPU.  y: device float32; y_ref: device float64.  Waits
  * for the stream and returns the value (negative on error). */

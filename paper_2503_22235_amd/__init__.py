@@ -18,7 +18,8 @@ __all__ = [
     "wm_nat_forward", "wm_layernorm", "wm_linear", "wm_processor_create",
     "wm_processor_destroy", "wm_processor_block", "wm_processor_step",
     "wm_schedule", "wm_rollout", "wm_relerr_l2", "grid_of", "LIB_PATH",
-    "wm_prof_enable", "wm_prof_collect", "PROF_KINDS",
+    "wm_prof_enable", "wm_prof_collect", "PROF_KINDS", "wm_serve_create",
+    "wm_serve_submit", "wm_serve_poll", "wm_serve_status", "wm_serve_destroy",
 ]
 
 WM_F32, WM_BF16, WM_FP8_E4M3 = 0, 1, 2
@@ -29,6 +30,17 @@ class WmError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libwm error {code}: {msg}")
         self.code = code
+
+
+class wm_serve_cfg(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int), ("state_bf16", ctypes.c_int),
+                ("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int)]
+
+
+class wm_req_stats(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("lead_hours", ctypes.c_int), ("steps", ctypes.c_int),
+                ("batches", ctypes.c_int), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
 
 
 class wm_grid(ctypes.Structure):
@@ -69,6 +81,12 @@ _SIGS = {
     "wm_rollout": (_int, [_vp, _vp, _vp, _int, _vp, _int, _vp]),
     "wm_relerr_l2": (ctypes.c_double, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "wm_prof_enable": (_int, [_vp, _int]),
+    "wm_serve_create": (_int, [_vp, _vp, _vp, ctypes.POINTER(wm_serve_cfg), ctypes.POINTER(_vp)]),
+    "wm_serve_submit": (_int, [_vp, _vp, _int, ctypes.POINTER(ctypes.c_uint64)]),
+    "wm_serve_poll": (_int, [_vp, ctypes.c_uint64, _vp, ctypes.POINTER(wm_req_stats)]),
+    "wm_serve_status": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
+                               ctypes.POINTER(_int)]),
+    "wm_serve_destroy": (None, [_vp]),
     "wm_prof_collect": (_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), _int]),
 }
 
@@ -240,3 +258,61 @@ def wm_relerr_l2(ctx, y, y_ref, n=None, stream=None) -> float:
     if r < 0:
         raise WmError(int(r), lib().wm_last_error().decode())
     return r
+
+
+class Server:
+    def __init__(self, handle, elems):
+        self.handle = handle
+        self.elems = elems
+
+    def close(self):
+        if self.handle:
+            lib().wm_serve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wm_serve_create(ctx, p6, p1, max_batch=8, state_bf16=True, hbm_budget_bytes=0, max_slots=0):
+    cfg = wm_serve_cfg(max_batch, 1 if state_bf16 else 0, hbm_budget_bytes, max_slots)
+    h = _vp()
+    _check(lib().wm_serve_create(ctx.handle, p6.handle, p1.handle, ctypes.byref(cfg), ctypes.byref(h)))
+    g = p6.grid
+    return Server(h.value, g.Z * g.Y * g.X * g.C)
+
+
+def wm_serve_submit(server, x0, lead_hours) -> int:
+    """x0: host float32 array of one state [Z, Y, X, C] (copied before return)."""
+    import numpy as np
+    a = np.ascontiguousarray(x0, dtype=np.float32)
+    if a.size != server.elems:
+        raise ValueError(f"state has {a.size} values, server expects {server.elems}")
+    rid = ctypes.c_uint64()
+    _check(lib().wm_serve_submit(server.handle, a.ctypes.data, lead_hours, ctypes.byref(rid)))
+    return rid.value
+
+
+def wm_serve_poll(server, rid, out=None):
+    """(done, stats): done is False while pending; out (float32 numpy) receives the state."""
+    st = wm_req_stats()
+    ptr = out.ctypes.data if out is not None else None
+    rc = lib().wm_serve_poll(server.handle, rid, ptr, ctypes.byref(st))
+    if rc == -3:
+        return False, None
+    _check(rc)
+    return True, {f: getattr(st, f) for f, _ in wm_req_stats._fields_}
+
+
+def wm_serve_status(server):
+    q, r, d, s = _int(), _int(), _int(), _int()
+    _check(lib().wm_serve_status(server.handle, ctypes.byref(q), ctypes.byref(r), ctypes.byref(d),
+                                 ctypes.byref(s)))
+    return {"queued": q.value, "running": r.value, "done": d.value, "slots": s.value}
+
+
+def wm_serve_destroy(server):
+    server.close()

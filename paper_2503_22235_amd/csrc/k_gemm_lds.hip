@@ -2,12 +2,17 @@
 //
 //   D[m][n] = sum_k A[m][k] * W[n][k]      (A: tokens x K, W: [out][in])
 //
-// Workgroup = 256 threads (4 waves, 2 x 2), tile BM x BN = 256 x 128, wave
-// tile 128 x 64 (8 x 4 MFMA 16x16x32 tiles; 32 MFMA per 32-wide k-step
-// against 12 fragment reads).  K advances in 64-element (128-byte) stages.
+// Workgroup = 256 threads (4 waves, 2 x 2), tile BM x BN (128 x 128 by
+// default: wave tile 64 x 64, 4 x 4 MFMA 16x16x32 tiles, 16 MFMA per
+// 32-wide k-step against 8 fragment reads; 256 x 128 also built).  K
+// advances in 64-element (128-byte) stages.
+// A workgroup owns one token tile and walks several output-feature tiles;
+// the stage stream runs on across tile boundaries, so the next tile's first
+// loads are in flight while the previous tile's epilogue runs.
 // Each stage is written straight from global memory into LDS by
-// buffer_load_dwordx4 ... lds (no register staging), issued two stages
-// ahead, so a load has two stages of MFMA work (~1.7 us) to land.  Rows of
+// buffer_load_dwordx4 ... lds (no register staging), issued STAGES-1
+// stages ahead; with two stages (64 KB) two workgroups share a CU and hide
+// each other's load latency and epilogues.  Rows of
 // A past M come back as zeros from the buffer range check, which handles
 // the ragged last token tile.  LDS rows are 128 bytes; their 16-byte chunks
 // are XOR-swizzled by (row >> 1) & 7 so the 16 rows a fragment read touches
@@ -15,6 +20,8 @@
 // the activation tile, so every lane ends up with four consecutive output
 // features of one token for the epilogue.  Tiles go out in an XCD-aware
 // order (consecutive ids on one XCD share an activation tile in its L2).
+#include <cstdlib>
+
 #include "kernels.hpp"
 
 namespace wm {
@@ -22,7 +29,6 @@ namespace glds {
 
 constexpr int NT = 256;
 constexpr int BK_BYTES = 128;
-constexpr int STAGES = 3;
 
 typedef __attribute__((address_space(3))) void lds_void;
 
@@ -46,17 +52,19 @@ __device__ __forceinline__ void store4(bf16 *p, f32x4 v) {
     *(uint2 *)p = u;
 }
 
+// Epilogue on four consecutive output features n..n+3 of token m.  For the
+// QKV scatter, `qkv_base` is the element offset of (part, head 0, token 0)
+// of the tile's part, `hc` the channel within the part and `qs` the Q scale
+// (1 for K and V): all but hc are uniform over the tile.
 template <int EPI>
-__device__ __forceinline__ void epilogue4(const EpiArgs &ep, int M, int N, int m, int n, f32x4 v) {
+__device__ __forceinline__ void epilogue4(const EpiArgs &ep, int M, int N, int m, int n, f32x4 v,
+                                          size_t qkv_base, int hc, float qs) {
     if (m >= M) return;
     const float4 b = *(const float4 *)(ep.bias + n);
     v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
     if constexpr (EPI == EPI_QKV) {
-        const int part = n / ep.C;
-        const int hc = n - part * ep.C;
-        const int h = hc >> 5, e = hc & 31;
-        if (part == 0) { v[0] *= ep.qscale; v[1] *= ep.qscale; v[2] *= ep.qscale; v[3] *= ep.qscale; }
-        store4((bf16 *)ep.out + (((size_t)(part * ep.H + h) * M + m) * 32 + e), v);
+        v[0] *= qs; v[1] *= qs; v[2] *= qs; v[3] *= qs;
+        store4((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * M + m) * 32 + (hc & 31), v);
     } else if constexpr (EPI == EPI_GELU) {
         v[0] = gelu_as(v[0]); v[1] = gelu_as(v[1]); v[2] = gelu_as(v[2]); v[3] = gelu_as(v[3]);
         store4((bf16 *)ep.out + (size_t)m * N + n, v);
@@ -78,9 +86,9 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <int BM, int BN, int EPI>
-__global__ __launch_bounds__(NT, 1) void gemm_lds_kernel(const bf16 *__restrict__ A, const bf16 *__restrict__ W,
-                                                         int M, int N, int K, EpiArgs ep) {
+template <int BM, int BN, int STAGES, int EPI>
+__global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const bf16 *__restrict__ A, const bf16 *__restrict__ W,
+                                                         int M, int N, int K, EpiArgs ep, int tpw) {
 #if defined(__HIP_DEVICE_COMPILE__)   // LDS-address-space builtins exist only in the device pass
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int TM = WM / 16, TN = WN / 16;
@@ -90,13 +98,16 @@ __global__ __launch_bounds__(NT, 1) void gemm_lds_kernel(const bf16 *__restrict_
     static_assert(ROWS % 32 == 0 && BM % 32 == 0, "rows per stage must split over 4 waves x 8 rows");
     extern __shared__ __align__(16) unsigned char smem[];
 
-    const int ntn = N / BN, ntm = (M + BM - 1) / BM, total = ntn * ntm;
+    const int ntn = N / BN, ntm = (M + BM - 1) / BM;
+    const int ngrp = (ntn + tpw - 1) / tpw, total = ngrp * ntm;
     const int per = (total + 7) >> 3;
     const int L = blockIdx.x;
     const int id = (L & 7) * per + (L >> 3);
     if (id >= total) return;
-    const int tn = id % ntn, tm = id / ntn;
-    const int m0 = tm * BM, n0 = tn * BN;
+    const int tg = id % ngrp, tm = id / ngrp;
+    const int m0 = tm * BM;
+    const int tn0 = tg * tpw;
+    const int nn = min(tpw, ntn - tn0);          // output-feature tiles of this workgroup
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
@@ -113,17 +124,22 @@ __global__ __launch_bounds__(NT, 1) void gemm_lds_kernel(const bf16 *__restrict_
     for (int i = 0; i < LPW; ++i) {
         const int row = 8 * (wave + 4 * i) + (lane >> 3);
         const int lc = (lane & 7) ^ swz(row);
-        voff[i] = i < BM / 32 ? (unsigned)(m0 + row) * Kb + lc * 16 : (unsigned)(n0 + row - BM) * Kb + lc * 16;
+        voff[i] = i < BM / 32 ? (unsigned)(m0 + row) * Kb + lc * 16
+                              : (unsigned)(tn0 * BN + row - BM) * Kb + lc * 16;
     }
-    auto issue = [&](int kt, int stage) {
+    const int nk = K / 64;
+    // stage s of the stream = k-stage (s % nk) of feature tile (s / nk)
+    auto issue = [&](int s, int stage) {
+        const int t = s / nk, kt = s - t * nk;
         unsigned char *sbase = smem + stage * STAGE_BYTES;
+        const unsigned wsoff = (unsigned)t * BN * Kb + kt * BK_BYTES;
 #pragma unroll
         for (int i = 0; i < LPW; ++i) {
             lds_void *dst = (lds_void *)(sbase + 8 * (wave + 4 * i) * BK_BYTES);
             if (i < BM / 32)
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(ars, dst, 16, voff[i], kt * BK_BYTES, 0, 0);
             else
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, dst, 16, voff[i], kt * BK_BYTES, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, dst, 16, voff[i], wsoff, 0, 0);
         }
     };
 
@@ -142,71 +158,92 @@ __global__ __launch_bounds__(NT, 1) void gemm_lds_kernel(const bf16 *__restrict_
         woff[ks] = (BM + wn * WN + r16) * BK_BYTES + pc;
     }
 
-    const int nk = K / 64;
-    issue(0, 0);
-    if (nk > 1) issue(1, 1);
-    for (int kt = 0; kt < nk; ++kt) {
-        // This wave's loads of stage kt have landed once at most the LPW
-        // loads of stage kt + 1 are outstanding; the barrier then makes all
-        // waves' parts of stage kt visible and frees the stage read in
-        // iteration kt - 1.  (A bare s_barrier: __syncthreads() would also
-        // drain the stage still in flight.)
-        if (kt + 1 < nk) wait_vmcnt<LPW>();
-        else wait_vmcnt<0>();
-        __builtin_amdgcn_s_barrier();
-        if (kt + 2 < nk) issue(kt + 2, (kt + 2) % STAGES);
-        const unsigned char *sb = smem + (kt % STAGES) * STAGE_BYTES;
+    const int S = nn * nk;
+    constexpr int AHEAD = STAGES - 1;                // stages in flight ahead of the one in use
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            bf16x8 af[TM], wf[TN];
+    for (int a = 0; a < AHEAD; ++a)
+        if (a < S) issue(a, a);
+    for (int t = 0; t < nn; ++t) {
+        for (int kt = 0; kt < nk; ++kt) {
+            const int st = t * nk + kt;
+            // This wave's loads of stage st have landed once at most the LPW
+            // loads of stage st + 1 are outstanding; the barrier then makes
+            // all waves' parts of stage st visible and frees the stage read
+            // in iteration st - 1.  (A bare s_barrier: __syncthreads() would
+            // also drain the stage still in flight.)
+            if constexpr (AHEAD == 2) {
+                if (st + 1 < S) wait_vmcnt<LPW>();
+                else wait_vmcnt<0>();
+            } else {
+                wait_vmcnt<0>();
+            }
+            __builtin_amdgcn_s_barrier();
+            if (st + AHEAD < S) issue(st + AHEAD, (st + AHEAD) % STAGES);
+            const unsigned char *sb = smem + (st % STAGES) * STAGE_BYTES;
 #pragma unroll
-            for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sb + aoff[ks] + 16 * i * BK_BYTES);
+            for (int ks = 0; ks < 2; ++ks) {
+                bf16x8 af[TM], wf[TN];
 #pragma unroll
-            for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sb + woff[ks] + 16 * j * BK_BYTES);
+                for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sb + aoff[ks] + 16 * i * BK_BYTES);
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
+                for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sb + woff[ks] + 16 * j * BK_BYTES);
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
-                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af[i], acc[j][i], 0, 0, 0);
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+                        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af[i], acc[j][i], 0, 0, 0);
+            }
         }
+        const int n0 = (tn0 + t) * BN;
+        // a feature tile never straddles Q/K/V (C is a multiple of BN)
+        const int part = EPI == EPI_QKV ? n0 / ep.C : 0;
+        const size_t qkv_base = (size_t)part * ep.H * M * 32;
+        const float qs = part == 0 ? ep.qscale : 1.0f;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int m = m0 + wm * WM + 16 * i + r16;
+                const int n = n0 + wn * WN + 16 * j + 4 * g;
+                epilogue4<EPI>(ep, M, N, m, n, acc[j][i], qkv_base, n - part * ep.C, qs);
+                acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
     }
-
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const int m = m0 + wm * WM + 16 * i + r16;
-            const int n = n0 + wn * WN + 16 * j + 4 * g;
-            epilogue4<EPI>(ep, M, N, m, n, acc[j][i]);
-        }
 #endif
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int STAGES>
 hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                       hipStream_t stream) {
     constexpr size_t lds = (size_t)STAGES * (BM + BN) * BK_BYTES;
     static bool attr_set = false;
     if (!attr_set) {
-        const void *fns[4] = {(const void *)gemm_lds_kernel<BM, BN, EPI_QKV>,
-                              (const void *)gemm_lds_kernel<BM, BN, EPI_GELU>,
-                              (const void *)gemm_lds_kernel<BM, BN, EPI_RESID>,
-                              (const void *)gemm_lds_kernel<BM, BN, EPI_STORE>};
+        const void *fns[4] = {(const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_QKV>,
+                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_GELU>,
+                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_RESID>,
+                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_STORE>};
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
         attr_set = true;
     }
-    const int total = (N / BN) * ((M + BM - 1) / BM);
+    const int ntn = N / BN;
+    // Output-feature tiles per workgroup (WM_GEMM_TPW overrides, for tuning).
+    static const int tpw_env = [] {
+        const char *v = getenv("WM_GEMM_TPW");
+        return v ? atoi(v) : 0;
+    }();
+    const int tpw = tpw_env > 0 ? (tpw_env < ntn ? tpw_env : ntn) : 1;
+    const int total = ((ntn + tpw - 1) / tpw) * ((M + BM - 1) / BM);
     const int grid = ((total + 7) >> 3) << 3;
     const bf16 *a = (const bf16 *)A;
     const bf16 *w = (const bf16 *)W;
     switch (epi) {
-    case EPI_QKV: gemm_lds_kernel<BM, BN, EPI_QKV><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep); break;
-    case EPI_GELU: gemm_lds_kernel<BM, BN, EPI_GELU><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep); break;
-    case EPI_RESID: gemm_lds_kernel<BM, BN, EPI_RESID><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep); break;
-    default: gemm_lds_kernel<BM, BN, EPI_STORE><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep); break;
+    case EPI_QKV: gemm_lds_kernel<BM, BN, STAGES, EPI_QKV><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
+    case EPI_GELU: gemm_lds_kernel<BM, BN, STAGES, EPI_GELU><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
+    case EPI_RESID: gemm_lds_kernel<BM, BN, STAGES, EPI_RESID><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
+    default: gemm_lds_kernel<BM, BN, STAGES, EPI_STORE><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
     }
     return hipGetLastError();
 }
@@ -222,7 +259,15 @@ bool gemm_lds_applies(int M, int N, int K) {
 
 hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                            hipStream_t stream) {
-    return launch_cfg<256, 128>(A, W, M, N, K, epi, ep, stream);
+    // Default: 128x128 tiles, 2 stages (64 KB of LDS, two workgroups per CU,
+    // so one's epilogue overlaps the other's MFMA work).  WM_GEMM_CFG=2
+    // selects 256x128 tiles with 3 stages (one workgroup per CU), for tuning.
+    static const int cfg = [] {
+        const char *v = getenv("WM_GEMM_CFG");
+        return v ? atoi(v) : 0;
+    }();
+    if (cfg == 2) return launch_cfg<256, 128, 3>(A, W, M, N, K, epi, ep, stream);
+    return launch_cfg<128, 128, 2>(A, W, M, N, K, epi, ep, stream);
 }
 
 }  // namespace wm

@@ -112,7 +112,29 @@ __global__ __launch_bounds__(256) void relerr_kernel(const float *__restrict__ y
     }
 }
 
+// Element-wise float32 <-> bfloat16 copy (RNE on the way down).
+template <bool SB, bool DB>
+__global__ __launch_bounds__(256) void convert_kernel(const void *__restrict__ src, void *__restrict__ dst,
+                                                      size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float v = SB ? bf2f(((const bf16 *)src)[i]) : ((const float *)src)[i];
+        if (DB) ((bf16 *)dst)[i] = f2bf(v);
+        else ((float *)dst)[i] = v;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_convert(const void *src, bool src_bf16, void *dst, bool dst_bf16, size_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (src_bf16 && !dst_bf16) convert_kernel<true, false><<<(unsigned)blocks, 256, 0, stream>>>(src, dst, n);
+    else if (!src_bf16 && dst_bf16) convert_kernel<false, true><<<(unsigned)blocks, 256, 0, stream>>>(src, dst, n);
+    else if (src_bf16) convert_kernel<true, true><<<(unsigned)blocks, 256, 0, stream>>>(src, dst, n);
+    else convert_kernel<false, false><<<(unsigned)blocks, 256, 0, stream>>>(src, dst, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_layernorm(const float *x, const float *gamma, const float *beta, void *out, bool out_bf16,
                             int M, int C, float eps, hipStream_t stream) {

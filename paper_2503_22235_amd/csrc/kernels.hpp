@@ -71,5 +71,7 @@ hipError_t launch_nat_indices(int Z, int Y, int X, int Kz, int Ky, int Kx,
 hipError_t launch_relerr(const float *y, const double *r, size_t n, double *acc,
                          hipStream_t stream);
 
-// --- layout copies for the standalone attention entry point ---------------
+// --- float32 <-> bfloat16 element copies (either direction, or plain copy)
+hipError_t launch_convert(const void *src, bool src_bf16, void *dst, bool dst_bf16, size_t n,
+                          hipStream_t stream);
 }  // namespace wm

@@ -82,3 +82,14 @@ def wm_status(name):
     text = open(os.path.join(ROOT, "include", "wm.h")).read()
     m = re.search(name + r"\s*=\s*(-?\d+)", text)
     return int(m.group(1))
+
+
+def test_serve_validation_without_gpu(wm):
+    L = wm.lib()
+    einval = wm_status("WM_EINVAL")
+    out = ctypes.c_void_p()
+    cfg = wm.wm_serve_cfg(4, 1, 0, 0)
+    assert L.wm_serve_create(None, None, None, ctypes.byref(cfg), ctypes.byref(out)) == einval
+    rid = ctypes.c_uint64()
+    assert L.wm_serve_submit(None, None, 6, ctypes.byref(rid)) == einval
+    assert L.wm_serve_poll(None, 1, None, None) == einval

@@ -1,0 +1,102 @@
+"""Continuous-batching server: results match a run alone and the rollout."""
+import time
+
+import numpy as np
+import pytest
+
+import wm_synth as S
+from oracle import wm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def drain(wm, srv, ids, shape, timeout=120.0):
+    out, stats = {}, {}
+    t0 = time.time()
+    while len(out) < len(ids):
+        for rid in ids:
+            if rid in out:
+                continue
+            buf = np.empty(shape, np.float32)
+            ok, st = wm.wm_serve_poll(srv, rid, buf)
+            if ok:
+                out[rid], stats[rid] = buf, st
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.002)
+    return out, stats
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2503_22235_amd as wm
+    assert torch.cuda.is_available()
+    ctx = wm.wm_ctx_create(0)
+    g = S.Grid(Z=4, Y=9, X=16, C=128, heads=4, Kz=3, Ky=5, Kx=5)
+    p6p = S.processor_params(g, 2, seed=1, proc=0)
+    p1p = S.processor_params(g, 2, seed=2, proc=1)
+    yield wm, torch, ctx, g, p6p, p1p
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,bf16_state", [(0, False), (1, True)])
+def test_serve_alone_equals_mix(env, prec, bf16_state):
+    wm, torch, ctx, g, p6p, p1p = env
+    p6 = wm.wm_processor_create(ctx, g, 2, 4, prec, p6p)
+    p1 = wm.wm_processor_create(ctx, g, 2, 4, prec, p1p)
+    shape = (g.Z, g.Y, g.X, g.C)
+    rng = np.random.default_rng(3)
+    leads = [int(v) for v in rng.integers(0, 20, size=10)] + [0, 13]
+    states = S.latent_state(g, len(leads), seed=0)
+    say("serve mix", prec, bf16_state, leads)
+    mix = wm.wm_serve_create(ctx, p6, p1, max_batch=4, state_bf16=bf16_state, max_slots=6)
+    ids = [wm.wm_serve_submit(mix, states[i], leads[i]) for i in range(len(leads))]
+    assert wm.wm_serve_status(mix)["slots"] == 6
+    res_mix, st_mix = drain(wm, mix, ids, shape)
+    mix.close()
+    alone = wm.wm_serve_create(ctx, p6, p1, max_batch=1, state_bf16=bf16_state, max_slots=1)
+    for i, lead in enumerate(leads):
+        rid = wm.wm_serve_submit(alone, states[i], lead)
+        r, st = drain(wm, alone, [rid], shape)
+        assert np.array_equal(r[rid], res_mix[ids[i]]), f"request {i} differs alone vs in the mix"
+        assert st[rid]["steps"] == len(O.schedule(lead))
+    alone.close()
+    batched = sum(1 for s in st_mix.values() if s["steps"] > 0)
+    assert batched > 0
+    for i, rid in enumerate(ids):
+        s = st_mix[rid]
+        assert s["t_submit"] <= s["t_admit"] <= s["t_done"]
+        assert s["lead_hours"] == leads[i]
+    if not bf16_state:
+        # float32 slots: the served state equals a direct rollout bit for bit
+        for i in (0, 3, 11):
+            xd = torch.from_numpy(states[i:i + 1].copy()).cuda()
+            wm.wm_rollout(ctx, p6, p1, 1, xd, leads[i])
+            assert np.array_equal(xd.cpu().numpy()[0], res_mix[ids[i]])
+    p6.close()
+    p1.close()
+
+
+def test_serve_result_against_oracle(env):
+    wm, torch, ctx, g, p6p, p1p = env
+    p6 = wm.wm_processor_create(ctx, g, 2, 4, 1, p6p)
+    p1 = wm.wm_processor_create(ctx, g, 2, 4, 1, p1p)
+    b6 = [S.split_block_params(g, p6p, b) for b in range(2)]
+    b1 = [S.split_block_params(g, p1p, b) for b in range(2)]
+    srv = wm.wm_serve_create(ctx, p6, p1, max_batch=2, state_bf16=True)
+    x = S.latent_state(g, 1, seed=5)[0]
+    rid = wm.wm_serve_submit(srv, x, 8)
+    out, _ = drain(wm, srv, [rid], x.shape)
+    ref = O.rollout(x, b6, b1, g, 8)
+    err = O.rel_l2(out[rid], ref)
+    say("serve bf16 lead 8 rel_l2", err)
+    assert err < 2e-2
+    with pytest.raises(wm.WmError):
+        wm.wm_serve_poll(srv, rid)            # already collected
+    srv.close()
+    p6.close()
+    p1.close()
