@@ -135,6 +135,21 @@ int wm_linear(int M, int N, int K, wm_precision prec, const void *a,
               const void *w, const float *bias, int epilogue, void *out,
               void *stream);
 
+/* FP8 quantization as the FP8 processors use it (OCP e4m3, max 448):
+ * out[i] = RNE(clamp(x[i] * mul, -448, 448)) as e4m3 codes.  x: device
+ * float32 [n]; out: device bytes [n]. */
+int wm_quantize_fp8(size_t n, const float *x, float mul, unsigned char *out,
+                    void *stream);
+
+/* One linear map on e4m3 operands with float32 accumulation:
+ *   r[m][n] = a_dequant * w_dequant * sum_k a8[m][k] * w8[n][k] + bias[n]
+ * a8 [M][K], w8 [N][K] device e4m3 codes; epilogue and out as wm_linear
+ * (0 and 1 write bfloat16).  N % 128 == 0, K % 128 == 0.  Waits for the
+ * stream before returning (it owns a temporary device scale). */
+int wm_linear_fp8(int M, int N, int K, const void *a8, float a_dequant,
+                  const void *w8, float w_dequant, const float *bias,
+                  int epilogue, void *out, void *stream);
+
 /* A processor: n_blocks pre-norm neighborhood-attention transformer blocks
  * (Sec. 2.1; App. A.2) with MLP width mlp_ratio*C, uploaded from HOST
  * float32 parameters in canonical order, per block:
@@ -143,7 +158,11 @@ int wm_linear(int M, int N, int K, wm_precision prec, const void *a,
  * Linear maps are [in][out] (y = x W + b); QKV columns are [Q | K | V].
  * The library copies and converts what it needs (the host array may be
  * freed on return) and owns the device copy until wm_processor_destroy.
- * Requires d = C/heads = 32 and C a multiple of 128. */
+ * Requires d = C/heads = 32 and C a multiple of 128.
+ * WM_FP8_E4M3 processors store the QKV and MLP matrices as e4m3 with
+ * per-tensor scales (amax / 448) and quantize the LayerNorm outputs and the
+ * GELU output per state and per tensor (dynamic amax / 448); attention and
+ * the output projection run in bfloat16. */
 int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks,
                         int mlp_ratio, wm_precision prec,
                         const float *host_params, wm_processor **out);

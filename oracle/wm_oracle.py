@@ -49,6 +49,7 @@ __all__ = [
     "window_axis", "neighbor_ids", "neighborhood_attention", "nat_at",
     "layer_norm", "gelu", "block", "block_at", "processor_step",
     "schedule", "rollout", "rel_l2", "nat_c", "oracle_threads",
+    "e4m3_values", "e4m3_encode", "e4m3_decode",
 ]
 
 LN_EPS = 1e-5
@@ -361,3 +362,44 @@ def rel_l2(y, y_ref):
     y = np.asarray(y, np.float64).ravel()
     r = np.asarray(y_ref, np.float64).ravel()
     return float(np.linalg.norm(y - r) / np.linalg.norm(r))
+
+
+# ---------------------------------------------------------------------------
+# OCP FP8 e4m3 ("e4m3fn"): 1 sign, 4 exponent (bias 7), 3 mantissa bits; no
+# infinities, one NaN pattern per sign (S.1111.111), max finite 448.  Used
+# to check the integer codes of the FP8 path (round to nearest, ties to the
+# even code, saturating at +-448).
+# ---------------------------------------------------------------------------
+def e4m3_values():
+    """Float value of each of the 128 non-negative codes (NaN for 0x7f)."""
+    vals = np.empty(128)
+    for code in range(128):
+        e, m = code >> 3, code & 7
+        if code == 0x7F:
+            vals[code] = np.nan
+        elif e == 0:
+            vals[code] = m / 8.0 * 2.0 ** -6
+        else:
+            vals[code] = (1.0 + m / 8.0) * 2.0 ** (e - 7)
+    return vals
+
+
+def e4m3_encode(x):
+    """Codes of x (float32 values), RNE, saturating to +-448."""
+    x = np.asarray(x, np.float64)
+    table = e4m3_values()[:127]                  # finite, increasing
+    a = np.minimum(np.abs(x), 448.0)
+    hi = np.searchsorted(table, a, side="left")  # first value >= a
+    hi = np.minimum(hi, 126)
+    lo = np.maximum(hi - 1, 0)
+    dlo, dhi = a - table[lo], table[hi] - a
+    pick_hi = (dhi < dlo) | ((dhi == dlo) & (hi % 2 == 0))
+    code = np.where(table[hi] == a, hi, np.where(pick_hi, hi, lo))
+    return (code | np.where(np.signbit(x) & (code != 0), 0x80, 0)).astype(np.uint8) | \
+        np.where(np.signbit(x) & (code == 0), 0x80, 0).astype(np.uint8)
+
+
+def e4m3_decode(codes):
+    codes = np.asarray(codes, np.uint8)
+    v = e4m3_values()[codes & 0x7F]
+    return np.where(codes & 0x80, -v, v)

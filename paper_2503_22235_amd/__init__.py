@@ -20,6 +20,7 @@ __all__ = [
     "wm_schedule", "wm_rollout", "wm_relerr_l2", "grid_of", "LIB_PATH",
     "wm_prof_enable", "wm_prof_collect", "PROF_KINDS", "wm_serve_create",
     "wm_serve_submit", "wm_serve_poll", "wm_serve_status", "wm_serve_destroy",
+    "wm_quantize_fp8", "wm_linear_fp8",
 ]
 
 WM_F32, WM_BF16, WM_FP8_E4M3 = 0, 1, 2
@@ -87,6 +88,8 @@ _SIGS = {
     "wm_serve_status": (_int, [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
                                ctypes.POINTER(_int)]),
     "wm_serve_destroy": (None, [_vp]),
+    "wm_quantize_fp8": (_int, [ctypes.c_size_t, _vp, ctypes.c_float, _vp, _vp]),
+    "wm_linear_fp8": (_int, [_int, _int, _int, _vp, ctypes.c_float, _vp, ctypes.c_float, _vp, _int, _vp, _vp]),
     "wm_prof_collect": (_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), _int]),
 }
 
@@ -236,6 +239,15 @@ def wm_schedule(lead_hours: int):
 def wm_rollout(ctx, p6, p1, B, x, lead_hours, stream=None):
     return _check(lib().wm_rollout(ctx.handle, p6.handle, p1.handle, B, _ptr(x), lead_hours,
                                    _stream(stream)))
+
+
+def wm_quantize_fp8(x, mul, out, stream=None):
+    return _check(lib().wm_quantize_fp8(x.numel(), _ptr(x), mul, _ptr(out), _stream(stream)))
+
+
+def wm_linear_fp8(M, N, K, a8, a_dequant, w8, w_dequant, bias, epilogue, out, stream=None):
+    return _check(lib().wm_linear_fp8(M, N, K, _ptr(a8), a_dequant, _ptr(w8), w_dequant, _ptr(bias),
+                                      epilogue, _ptr(out), _stream(stream)))
 
 
 def wm_prof_enable(ctx, on=True):

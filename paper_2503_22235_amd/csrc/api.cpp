@@ -2,6 +2,7 @@
 // sequences and the small helpers.  Declarations and contracts: wm.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -212,6 +213,46 @@ int wm_linear(int M, int N, int K, wm_precision prec, const void *a, const void 
     return e == hipSuccess ? WM_OK : hip_fail(e, "gemm launch");
 }
 
+int wm_quantize_fp8(size_t n, const float *x, float mul, unsigned char *out, void *stream) {
+    if (n == 0) return WM_OK;
+    if (!x || !out) return fail(WM_EINVAL, "NULL tensor");
+    hipError_t e = launch_quant_f32(x, n, mul, out, (hipStream_t)stream);
+    return e == hipSuccess ? WM_OK : hip_fail(e, "quantize launch");
+}
+
+int wm_linear_fp8(int M, int N, int K, const void *a8, float a_dequant, const void *w8, float w_dequant,
+                  const float *bias, int epilogue, void *out, void *stream) {
+    if (M < 0 || N <= 0 || K <= 0) return fail(WM_EINVAL, "bad GEMM shape");
+    if (N % 128 || K % 128) return fail(WM_EINVAL, "N and K must be multiples of 128");
+    if (epilogue < 0 || epilogue > 2) return fail(WM_EINVAL, "epilogue must be 0, 1 or 2");
+    if (M == 0) return WM_OK;
+    if (!a8 || !w8 || !bias || !out) return fail(WM_EINVAL, "NULL tensor");
+    // one state holding all M rows; its amax is a_dequant * 448
+    float *amax_dev = nullptr;
+    hipError_t e = hipMalloc(&amax_dev, sizeof(float));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    const float amax = a_dequant * 448.0f;
+    hipStream_t s = (hipStream_t)stream;
+    if ((e = hipMemcpyAsync(amax_dev, &amax, sizeof amax, hipMemcpyHostToDevice, s)) != hipSuccess) {
+        (void)hipFree(amax_dev);
+        return hip_fail(e, "copy");
+    }
+    EpiArgs ep{};
+    ep.bias = bias;
+    ep.a_amax = amax_dev;
+    ep.w_dequant = w_dequant;
+    ep.T = M;
+    EpiKind kind = EPI_STORE;
+    if (epilogue == 1) { kind = EPI_GELU; ep.out = out; }
+    else if (epilogue == 2) { kind = EPI_RESID; ep.resid = (float *)out; }
+    else ep.out = out;
+    e = launch_gemm_fp8(a8, w8, M, N, K, kind, ep, s);
+    const hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(amax_dev);
+    if (e != hipSuccess) return hip_fail(e, "gemm launch");
+    return e2 == hipSuccess ? WM_OK : hip_fail(e2, "sync");
+}
+
 int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_ratio, wm_precision prec,
                         const float *host_params, wm_processor **out) {
     if (!out) return fail(WM_EINVAL, "out is NULL");
@@ -221,7 +262,8 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
     if (rc) return rc;
     if (n_blocks < 1 || n_blocks > 64) return fail(WM_EINVAL, "n_blocks must be 1..64");
     if (mlp_ratio < 1 || mlp_ratio > 8) return fail(WM_EINVAL, "mlp_ratio must be 1..8");
-    if (prec != WM_F32 && prec != WM_BF16) return fail(WM_EINVAL, "processor precision %d not supported", (int)prec);
+    if (prec != WM_F32 && prec != WM_BF16 && prec != WM_FP8_E4M3)
+        return fail(WM_EINVAL, "processor precision %d not supported", (int)prec);
     if (!host_params) return fail(WM_EINVAL, "host_params is NULL");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -235,12 +277,16 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
     p->device = ctx->device;
     const int C = g->C, F = C * mlp_ratio, H = g->heads;
     const size_t nrpb = (size_t)H * (2 * g->Kz - 1) * (2 * g->Ky - 1) * (2 * g->Kx - 1);
-    const size_t esz = prec == WM_BF16 ? 2 : 4;
+    // Bytes per weight element: float32, bfloat16, or (FP8) e4m3 for the QKV
+    // and MLP matrices with the output projection kept in bfloat16.
+    const bool fp8 = prec == WM_FP8_E4M3;
+    const size_t esz = prec == WM_F32 ? 4 : 2;
+    const size_t esz_big = fp8 ? 1 : esz;
     // Device image per block: float32 vectors, then the four transposed weights.
     const size_t nvec = 2 * C + 3 * C + nrpb + C + 2 * C + F + C;
-    const size_t nw = (size_t)3 * C * C + (size_t)C * C + (size_t)F * C * 2;
+    const size_t nw_bytes = ((size_t)3 * C * C + (size_t)F * C * 2) * esz_big + (size_t)C * C * esz + 4 * 256;
     auto align = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t blk_bytes = align(nvec * 4) + align(nw * esz) + 4 * 256;
+    const size_t blk_bytes = align(nvec * 4) + align(nw_bytes) + 4 * 256;
     p->bytes = blk_bytes * n_blocks;
     if ((e = hipMalloc(&p->mem, p->bytes)) != hipSuccess) {
         delete p;
@@ -260,9 +306,20 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
             *dst = (const float *)(dev + off);
             off += n * 4;
         };
-        auto put_wt = [&](const float *s, int in, int outn, const void **dst) {
+        // source [in][out] -> device [out][in]; returns the fp8 dequant scale
+        auto put_wt = [&](const float *s, int in, int outn, const void **dst, bool q8) -> float {
             off = align(off);
-            // source [in][out] -> device [out][in]
+            if (q8) {
+                float amax = 0.f;
+                for (size_t i = 0; i < (size_t)in * outn; ++i) amax = std::max(amax, std::fabs(s[i]));
+                const float inv = amax > 0.f ? 448.0f / amax : 1.0f;
+                unsigned char *d = img.data() + off;
+                for (int o = 0; o < outn; ++o)
+                    for (int i = 0; i < in; ++i) d[(size_t)o * in + i] = host_fp8_e4m3(s[(size_t)i * outn + o] * inv);
+                *dst = dev + off;
+                off += (size_t)in * outn;
+                return amax > 0.f ? amax / 448.0f : 1.0f;
+            }
             if (esz == 2) {
                 uint16_t *d = (uint16_t *)(img.data() + off);
                 for (int o = 0; o < outn; ++o)
@@ -274,6 +331,7 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
             }
             *dst = dev + off;
             off += (size_t)in * outn * esz;
+            return 1.0f;
         };
         const float *ln1_g = src; src += C;
         const float *ln1_b = src; src += C;
@@ -297,10 +355,10 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
         put_vec(ln2_b, C, 1.f, &bw.ln2_b);
         put_vec(b_1, F, 1.f, &bw.b_1);
         put_vec(b_2, C, 1.f, &bw.b_2);
-        put_wt(w_qkv, C, 3 * C, &bw.w_qkv);
-        put_wt(w_o, C, C, &bw.w_o);
-        put_wt(w_1, C, F, &bw.w_1);
-        put_wt(w_2, F, C, &bw.w_2);
+        bw.dq_qkv = put_wt(w_qkv, C, 3 * C, &bw.w_qkv, fp8);
+        put_wt(w_o, C, C, &bw.w_o, false);
+        bw.dq_1 = put_wt(w_1, C, F, &bw.w_1, fp8);
+        bw.dq_2 = put_wt(w_2, F, C, &bw.w_2, fp8);
         if ((e = hipMemcpy(dev, img.data(), blk_bytes, hipMemcpyHostToDevice)) != hipSuccess) {
             (void)hipFree(p->mem);
             delete p;

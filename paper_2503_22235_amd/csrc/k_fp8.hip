@@ -1,0 +1,164 @@
+// FP8 (OCP e4m3, max 448) quantization for the FP8 processor precision.
+//
+// A tensor quantized per state uses the dequantization scale
+//   s = amax / 448   (amax = max |value| over the state's tokens),
+// and codes q = RNE(clamp(value * (448 / amax), -448, 448)).  amax values
+// are kept as float bits and combined with unsigned atomicMax (|v| >= 0, so
+// the bit patterns order like the values).
+#include "kernels.hpp"
+
+namespace wm {
+namespace {
+
+__device__ __forceinline__ float clamp448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
+
+// Four floats -> four e4m3 codes (byte i = value i), round to nearest even.
+__device__ __forceinline__ unsigned pack4_fp8(float a, float b, float c, float d) {
+    unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(a), clamp448(b), 0, false);
+    return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(c), clamp448(d), (int)w, true);
+}
+
+__device__ __forceinline__ float inv_scale(float amax) { return amax > 0.f ? 448.0f / amax : 1.0f; }
+
+// Pass 1 of an FP8 LayerNorm: per-state amax of the LN output.
+template <int VPT>
+__global__ __launch_bounds__(256) void ln_amax_kernel(const float *__restrict__ x, const float *__restrict__ gamma,
+                                                      const float *__restrict__ beta, int M, int T, float eps,
+                                                      unsigned *__restrict__ amax) {
+    constexpr int C = VPT * 64;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= M) return;
+    const int lane = threadIdx.x & 63;
+    const float *xr = x + (size_t)row * C;
+    float v[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT / 2; ++j) {
+        const float2 t = *(const float2 *)(xr + 2 * (j * 64 + lane));
+        v[2 * j] = t.x;
+        v[2 * j + 1] = t.y;
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) s += v[i];
+    const float mean = wave_sum(s) * (1.0f / C);
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) q += (v[i] - mean) * (v[i] - mean);
+    const float rstd = 1.0f / sqrtf(wave_sum(q) * (1.0f / C) + eps);
+    float m = 0.f;
+#pragma unroll
+    for (int j = 0; j < VPT / 2; ++j)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int c = 2 * (j * 64 + lane) + u;
+            m = fmaxf(m, fabsf((v[2 * j + u] - mean) * rstd * gamma[c] + beta[c]));
+        }
+    m = wave_max(m);
+    if (lane == 0) atomicMax(amax + row / T, __float_as_uint(m));
+}
+
+// Pass 2: LayerNorm, then quantize with the state's scale.
+template <int VPT>
+__global__ __launch_bounds__(256) void ln_quant_kernel(const float *__restrict__ x, const float *__restrict__ gamma,
+                                                       const float *__restrict__ beta, int M, int T, float eps,
+                                                       const float *__restrict__ amax, unsigned char *__restrict__ out) {
+    constexpr int C = VPT * 64;
+    static_assert(VPT % 4 == 0 || VPT == 2, "per-lane chunk");
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= M) return;
+    const int lane = threadIdx.x & 63;
+    const float *xr = x + (size_t)row * C;
+    float v[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT / 2; ++j) {
+        const float2 t = *(const float2 *)(xr + 2 * (j * 64 + lane));
+        v[2 * j] = t.x;
+        v[2 * j + 1] = t.y;
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) s += v[i];
+    const float mean = wave_sum(s) * (1.0f / C);
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) q += (v[i] - mean) * (v[i] - mean);
+    const float rstd = 1.0f / sqrtf(wave_sum(q) * (1.0f / C) + eps);
+    const float inv = inv_scale(amax[row / T]);
+    unsigned char *o = out + (size_t)row * C;
+#pragma unroll
+    for (int j = 0; j < VPT / 2; ++j) {
+        const int c = 2 * (j * 64 + lane);
+        const float y0 = ((v[2 * j] - mean) * rstd * gamma[c] + beta[c]) * inv;
+        const float y1 = ((v[2 * j + 1] - mean) * rstd * gamma[c + 1] + beta[c + 1]) * inv;
+        const unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(y0), clamp448(y1), 0, false);
+        *(unsigned short *)(o + c) = (unsigned short)(w & 0xffffu);
+    }
+}
+
+// bf16 [B*T][F] -> e4m3 with the scale of each row's state.
+__global__ __launch_bounds__(256) void quant_rows_kernel(const bf16 *__restrict__ in, size_t n4, int F, long T,
+                                                         const float *__restrict__ amax,
+                                                         unsigned char *__restrict__ out) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (size_t)gridDim.x * 256) {
+        const size_t e = 4 * i;
+        const long row = (long)(e / F);
+        const float inv = inv_scale(amax[row / T]);
+        const uint2 u = *(const uint2 *)(in + e);
+        const float a = bf_bits2f((unsigned short)(u.x & 0xffff)) * inv;
+        const float b = bf_bits2f((unsigned short)(u.x >> 16)) * inv;
+        const float c = bf_bits2f((unsigned short)(u.y & 0xffff)) * inv;
+        const float d = bf_bits2f((unsigned short)(u.y >> 16)) * inv;
+        *(unsigned *)(out + e) = pack4_fp8(a, b, c, d);
+    }
+}
+
+// float32 -> e4m3 with one given multiplier (codes = RNE(clamp(x * mul))).
+__global__ __launch_bounds__(256) void quant_f32_kernel(const float *__restrict__ in, size_t n, float mul,
+                                                        unsigned char *__restrict__ out) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(in[i] * mul), 0.f, 0, false);
+        out[i] = (unsigned char)(w & 0xff);
+    }
+}
+
+template <int VPT>
+hipError_t ln_fp8(const float *x, const float *g, const float *b, int M, int T, float eps, unsigned *amax,
+                  unsigned char *out, hipStream_t s) {
+    const int grid = (M + 3) / 4;
+    ln_amax_kernel<VPT><<<grid, 256, 0, s>>>(x, g, b, M, T, eps, amax);
+    ln_quant_kernel<VPT><<<grid, 256, 0, s>>>(x, g, b, M, T, eps, (const float *)amax, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_layernorm_fp8(const float *x, const float *gamma, const float *beta, int M, int C, int T,
+                                float eps, unsigned *amax, unsigned char *out, hipStream_t stream) {
+    if (M <= 0) return hipSuccess;
+    switch (C) {
+    case 128: return ln_fp8<2>(x, gamma, beta, M, T, eps, amax, out, stream);
+    case 256: return ln_fp8<4>(x, gamma, beta, M, T, eps, amax, out, stream);
+    case 512: return ln_fp8<8>(x, gamma, beta, M, T, eps, amax, out, stream);
+    case 1024: return ln_fp8<16>(x, gamma, beta, M, T, eps, amax, out, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_quant_rows(const void *in_bf16, size_t n, int F, long T, const float *amax, unsigned char *out,
+                             hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n / 4 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    quant_rows_kernel<<<(unsigned)blocks, 256, 0, stream>>>((const bf16 *)in_bf16, n / 4, F, T, amax, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_quant_f32(const float *in, size_t n, float mul, unsigned char *out, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    quant_f32_kernel<<<(unsigned)blocks, 256, 0, stream>>>(in, n, mul, out);
+    return hipGetLastError();
+}
+
+}  // namespace wm

@@ -57,9 +57,10 @@ __device__ __forceinline__ void store4(bf16 *p, f32x4 v) {
 // of the tile's part, `hc` the channel within the part and `qs` the Q scale
 // (1 for K and V): all but hc are uniform over the tile.
 template <int EPI>
-__device__ __forceinline__ void epilogue4(const EpiArgs &ep, int M, int N, int m, int n, f32x4 v,
-                                          size_t qkv_base, int hc, float qs) {
-    if (m >= M) return;
+__device__ __forceinline__ float epilogue4(const EpiArgs &ep, int M, int N, int m, int n, f32x4 v,
+                                           size_t qkv_base, int hc, float qs, float dq) {
+    if (m >= M) return 0.f;
+    v[0] *= dq; v[1] *= dq; v[2] *= dq; v[3] *= dq;
     const float4 b = *(const float4 *)(ep.bias + n);
     v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
     if constexpr (EPI == EPI_QKV) {
@@ -76,6 +77,7 @@ __device__ __forceinline__ void epilogue4(const EpiArgs &ep, int M, int N, int m
     } else {
         store4((bf16 *)ep.out + (size_t)m * N + n, v);
     }
+    return fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
 }
 
 // s_waitcnt with vmcnt <= n and no wait on the other counters (gfx9 encoding:
@@ -86,8 +88,10 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <int BM, int BN, int STAGES, int EPI>
-__global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const bf16 *__restrict__ A, const bf16 *__restrict__ W,
+// FP8: operands are e4m3 bytes (128 k-values per 128-byte stage, MFMA
+// 16x16x32 fp8 with 8-byte fragments); the epilogue dequantizes per row.
+template <int BM, int BN, int STAGES, int EPI, bool FP8>
+__global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const void *__restrict__ A, const void *__restrict__ W,
                                                          int M, int N, int K, EpiArgs ep, int tpw) {
 #if defined(__HIP_DEVICE_COMPILE__)   // LDS-address-space builtins exist only in the device pass
     constexpr int WM = BM / 2, WN = BN / 2;
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int g = lane >> 4, r16 = lane & 15;
-    const unsigned Kb = (unsigned)K * 2;
+    const unsigned Kb = (unsigned)K * (FP8 ? 1 : 2);
     const __amdgpu_buffer_rsrc_t ars = make_rsrc(A, (unsigned)M * Kb);
     const __amdgpu_buffer_rsrc_t wrs = make_rsrc(W, (unsigned)N * Kb);
 
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
         voff[i] = i < BM / 32 ? (unsigned)(m0 + row) * Kb + lc * 16
                               : (unsigned)(tn0 * BN + row - BM) * Kb + lc * 16;
     }
-    const int nk = K / 64;
+    const int nk = K / (FP8 ? 128 : 64);
     // stage s of the stream = k-stage (s % nk) of feature tile (s / nk)
     auto issue = [&](int s, int stage) {
         const int t = s / nk, kt = s - t * nk;
@@ -149,11 +153,15 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
 #pragma unroll
         for (int i = 0; i < TM; ++i) acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // lane-constant fragment offsets inside a stage (swizzle depends on r16 only)
-    int aoff[2], woff[2];
+    // lane-constant fragment offsets inside a stage (swizzle depends on r16
+    // only): bf16 k-step ks reads 16 bytes at k = 32ks + 8g; fp8 k-step ks
+    // reads 8 bytes at k = 32ks + 8g.
+    constexpr int KSTEPS = FP8 ? 4 : 2;
+    int aoff[KSTEPS], woff[KSTEPS];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-        const int pc = ((4 * ks + g) ^ ((r16 >> 1) & 7)) << 4;
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        const int pc = FP8 ? ((((2 * ks + (g >> 1)) ^ ((r16 >> 1) & 7)) << 4) + 8 * (g & 1))
+                           : (((4 * ks + g) ^ ((r16 >> 1) & 7)) << 4);
         aoff[ks] = (wm * WM + r16) * BK_BYTES + pc;
         woff[ks] = (BM + wn * WN + r16) * BK_BYTES + pc;
     }
@@ -181,17 +189,30 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
             if (st + AHEAD < S) issue(st + AHEAD, (st + AHEAD) % STAGES);
             const unsigned char *sb = smem + (st % STAGES) * STAGE_BYTES;
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                bf16x8 af[TM], wf[TN];
+            for (int ks = 0; ks < KSTEPS; ++ks) {
+                if constexpr (FP8) {
+                    long af[TM], wf[TN];
 #pragma unroll
-                for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sb + aoff[ks] + 16 * i * BK_BYTES);
+                    for (int i = 0; i < TM; ++i) af[i] = *(const long *)(sb + aoff[ks] + 16 * i * BK_BYTES);
 #pragma unroll
-                for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sb + woff[ks] + 16 * j * BK_BYTES);
+                    for (int j = 0; j < TN; ++j) wf[j] = *(const long *)(sb + woff[ks] + 16 * j * BK_BYTES);
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
+                    for (int j = 0; j < TN; ++j)
 #pragma unroll
-                    for (int i = 0; i < TM; ++i)
-                        acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af[i], acc[j][i], 0, 0, 0);
+                        for (int i = 0; i < TM; ++i)
+                            acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(wf[j], af[i], acc[j][i], 0, 0, 0);
+                } else {
+                    bf16x8 af[TM], wf[TN];
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sb + aoff[ks] + 16 * i * BK_BYTES);
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sb + woff[ks] + 16 * j * BK_BYTES);
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int i = 0; i < TM; ++i)
+                            acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af[i], acc[j][i], 0, 0, 0);
+                }
             }
         }
         const int n0 = (tn0 + t) * BN;
@@ -199,29 +220,54 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
         const int part = EPI == EPI_QKV ? n0 / ep.C : 0;
         const size_t qkv_base = (size_t)part * ep.H * M * 32;
         const float qs = part == 0 ? ep.qscale : 1.0f;
+        // per-row dequantization (fp8) and per-state amax of the outputs
+        float dq[TM];
+        int srow[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int m = min(m0 + wm * WM + 16 * i + r16, M - 1);
+            srow[i] = FP8 || ep.out_amax ? (int)(m / ep.T) : 0;
+            dq[i] = FP8 ? ep.a_amax[srow[i]] * (1.0f / 448.0f) * ep.w_dequant : 1.0f;
+        }
+        const int s_lo = ep.out_amax ? (int)(min(m0, M - 1) / ep.T) : 0;
+        float mlo = 0.f, mhi = 0.f;
 #pragma unroll
         for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
                 const int m = m0 + wm * WM + 16 * i + r16;
                 const int n = n0 + wn * WN + 16 * j + 4 * g;
-                epilogue4<EPI>(ep, M, N, m, n, acc[j][i], qkv_base, n - part * ep.C, qs);
+                const float a = epilogue4<EPI>(ep, M, N, m, n, acc[j][i], qkv_base, n - part * ep.C, qs, dq[i]);
                 acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (ep.out_amax) {
+                    if (srow[i] == s_lo) mlo = fmaxf(mlo, a);
+                    else if (srow[i] == s_lo + 1) mhi = fmaxf(mhi, a);
+                    else if (m < M) atomicMax(ep.out_amax + srow[i] * ep.amax_stride + part, __float_as_uint(a));
+                }
             }
+        if (ep.out_amax) {
+            mlo = wave_max(mlo);
+            mhi = wave_max(mhi);
+            if (lane == 0) {
+                atomicMax(ep.out_amax + s_lo * ep.amax_stride + part, __float_as_uint(mlo));
+                if ((long)(s_lo + 1) * ep.T < M)
+                    atomicMax(ep.out_amax + (s_lo + 1) * ep.amax_stride + part, __float_as_uint(mhi));
+            }
+        }
     }
 #endif
 }
 
-template <int BM, int BN, int STAGES>
+template <int BM, int BN, int STAGES, bool FP8>
 hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                       hipStream_t stream) {
     constexpr size_t lds = (size_t)STAGES * (BM + BN) * BK_BYTES;
     static bool attr_set = false;
     if (!attr_set) {
-        const void *fns[4] = {(const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_QKV>,
-                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_GELU>,
-                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_RESID>,
-                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_STORE>};
+        const void *fns[4] = {(const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_QKV, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_GELU, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_RESID, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_STORE, FP8>};
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
@@ -237,13 +283,13 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
     const int tpw = tpw_env > 0 ? (tpw_env < ntn ? tpw_env : ntn) : 1;
     const int total = ((ntn + tpw - 1) / tpw) * ((M + BM - 1) / BM);
     const int grid = ((total + 7) >> 3) << 3;
-    const bf16 *a = (const bf16 *)A;
-    const bf16 *w = (const bf16 *)W;
+    const void *a = A;
+    const void *w = W;
     switch (epi) {
-    case EPI_QKV: gemm_lds_kernel<BM, BN, STAGES, EPI_QKV><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
-    case EPI_GELU: gemm_lds_kernel<BM, BN, STAGES, EPI_GELU><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
-    case EPI_RESID: gemm_lds_kernel<BM, BN, STAGES, EPI_RESID><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
-    default: gemm_lds_kernel<BM, BN, STAGES, EPI_STORE><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
+    case EPI_QKV: gemm_lds_kernel<BM, BN, STAGES, EPI_QKV, FP8><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
+    case EPI_GELU: gemm_lds_kernel<BM, BN, STAGES, EPI_GELU, FP8><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
+    case EPI_RESID: gemm_lds_kernel<BM, BN, STAGES, EPI_RESID, FP8><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
+    default: gemm_lds_kernel<BM, BN, STAGES, EPI_STORE, FP8><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
     }
     return hipGetLastError();
 }
@@ -266,8 +312,15 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
         const char *v = getenv("WM_GEMM_CFG");
         return v ? atoi(v) : 0;
     }();
-    if (cfg == 2) return launch_cfg<256, 128, 3>(A, W, M, N, K, epi, ep, stream);
-    return launch_cfg<128, 128, 2>(A, W, M, N, K, epi, ep, stream);
+    if (cfg == 2) return launch_cfg<256, 128, 3, false>(A, W, M, N, K, epi, ep, stream);
+    return launch_cfg<128, 128, 2, false>(A, W, M, N, K, epi, ep, stream);
+}
+
+hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
+                           hipStream_t stream) {
+    if (M <= 0) return hipSuccess;
+    if (N % 128 || K % 128 || (unsigned long long)M * K >= (1ull << 32)) return hipErrorInvalidValue;
+    return launch_cfg<128, 128, 2, true>(A, W, M, N, K, epi, ep, stream);
 }
 
 }  // namespace wm

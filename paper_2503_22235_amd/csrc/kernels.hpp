@@ -28,6 +28,14 @@ struct EpiArgs {
     float *resid;       // EPI_RESID target
     int C, H;           // EPI_QKV: model width and heads (d = 32)
     float qscale;       // EPI_QKV: factor on Q columns
+    // FP8 operands: acc * (a_amax[state of row] / 448) * w_dequant
+    const float *a_amax;
+    float w_dequant;
+    long T;             // tokens per state
+    // optional: per-state amax of the stored outputs (float bits), index
+    // state * amax_stride + (QKV part or 0)
+    unsigned *out_amax;
+    int amax_stride;
 };
 // A: [M][K], W: [N][K], both bf16 (a_bf16) or float32.  Output element
 // type follows the operands (bf16 or float) except EPI_RESID (float32).
@@ -36,10 +44,24 @@ struct EpiArgs {
 hipError_t launch_gemm(const void *A, const void *W, int M, int N, int K, bool a_bf16,
                        EpiKind epi, const EpiArgs &ep, hipStream_t stream);
 
-// The 256x128 LDS-ring bf16 kernel (taken by launch_gemm when it applies).
+// The LDS-ring bf16 kernel (taken by launch_gemm when it applies).
 bool gemm_lds_applies(int M, int N, int K);
 hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, EpiKind epi,
                            const EpiArgs &ep, hipStream_t stream);
+// e4m3 operands (A [M][K], W [N][K] bytes); needs N % 128 == 0, K % 128 == 0.
+hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, EpiKind epi,
+                           const EpiArgs &ep, hipStream_t stream);
+
+// --- FP8 quantization (OCP e4m3; per-state scale amax / 448) --------------
+// Two-pass LayerNorm: per-state amax of the LN output (atomicMax into
+// amax[state], which the caller zeroes), then LN + quantize.
+hipError_t launch_layernorm_fp8(const float *x, const float *gamma, const float *beta, int M, int C, int T,
+                                float eps, unsigned *amax, unsigned char *out, hipStream_t stream);
+// bf16 rows [M][F] -> e4m3 with each row's state scale (n % 4 == 0, F % 4 == 0)
+hipError_t launch_quant_rows(const void *in_bf16, size_t n, int F, long T, const float *amax,
+                             unsigned char *out, hipStream_t stream);
+// float32 -> e4m3 codes = RNE(clamp(x * mul, +-448))
+hipError_t launch_quant_f32(const float *in, size_t n, float mul, unsigned char *out, hipStream_t stream);
 
 // --- 3-D neighborhood attention ------------------------------------------
 struct NatArgs {

@@ -1,13 +1,22 @@
 // Launch sequences of a processor block and step, and the greedy schedule.
+#include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "runtime.hpp"
 
 namespace wm {
 
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 size_t block_workspace_bytes(const wm_processor *p, int B) {
     const size_t M = (size_t)B * p->g.Z * p->g.Y * p->g.X;
     const size_t C = p->g.C, F = C * p->mlp;
+    if (p->prec == WM_FP8_E4M3) {
+        // u8/w8 | qkv or h (bf16) | o (bf16) | h8 | bias tables | amax slots
+        return al256(M * C) + al256(M * std::max(3 * C, F) * 2) + al256(M * C * 2) + al256(M * F) +
+               (size_t)p->g.heads * NAT_TBL_WS_FLOATS * 4 + al256((size_t)B * 8 * 4);
+    }
     const size_t esz = p->prec == WM_BF16 ? 2 : 4;
     const size_t big = (3 * C > F ? 3 * C : F);
     const size_t act = (M * C * esz + 255) & ~(size_t)255;
@@ -51,7 +60,10 @@ int prof_end(wm_ctx *ctx, hipStream_t s) {
 //   written head-major); o = NA(q, k, v); x += o W_o + b_o;
 //   w = LN2(x); h = GELU(w W_1 + b_1); x += h W_2 + b_2.
 // u, o and w share one buffer; qkv and h share the other.
+static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s);
+
 int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s) {
+    if (p->prec == WM_FP8_E4M3) return run_block_fp8(ctx, p, block, B, x, s);
     const wm_grid &g = p->g;
     const BlockWeights &w = p->blk[block];
     const long T = (long)g.Z * g.Y * g.X;
@@ -115,12 +127,119 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     return WM_OK;
 }
 
+// FP8 block: LayerNorms quantize their outputs per state (two passes), the
+// QKV and MLP GEMMs run on e4m3 operands (per-tensor weight scales, per-state
+// activation scales), the QKV and MLP1 epilogues record per-state amax of
+// their bf16 outputs, the GELU output is quantized before MLP2; attention and
+// the output projection run in bf16; the residual stream stays float32.
+static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s) {
+    const wm_grid &g = p->g;
+    const BlockWeights &w = p->blk[block];
+    const long T = (long)g.Z * g.Y * g.X;
+    const int M = (int)(B * T);
+    const int C = g.C, F = C * p->mlp, H = g.heads;
+    char *base = (char *)ctx->ws;
+    unsigned char *act8 = (unsigned char *)base;
+    char *big = base + al256((size_t)M * C);
+    char *obuf = big + al256((size_t)M * std::max(3 * C, F) * 2);
+    unsigned char *h8 = (unsigned char *)(obuf + al256((size_t)M * C * 2));
+    float *tbl_ws = (float *)((char *)h8 + al256((size_t)M * F));
+    unsigned *amax = (unsigned *)((char *)tbl_ws + (size_t)H * NAT_TBL_WS_FLOATS * 4);
+    unsigned *amax_u = amax, *amax_qkv = amax + B, *amax_w = amax + 4 * B, *amax_h = amax + 5 * B;
+    hipError_t e;
+    int rc;
+#define WM_TIMED(kind, call, what)                                  \
+    if ((rc = prof_begin(ctx, s, kind)) != WM_OK) return rc;        \
+    if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
+    if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
+    if ((e = hipMemsetAsync(amax, 0, (size_t)B * 8 * 4, s)) != hipSuccess) return hip_fail(e, "amax reset");
+    WM_TIMED(PK_LN1, launch_layernorm_fp8(x, w.ln1_g, w.ln1_b, M, C, (int)T, 1e-5f, amax_u, act8, s), "LN1")
+    EpiArgs ep{};
+    ep.bias = w.b_qkv;
+    ep.out = big;
+    ep.C = C;
+    ep.H = H;
+    ep.qscale = LOG2E / std::sqrt(32.0f);
+    ep.a_amax = (const float *)amax_u;
+    ep.w_dequant = w.dq_qkv;
+    ep.T = T;
+    ep.out_amax = amax_qkv;
+    ep.amax_stride = 3;
+    WM_TIMED(PK_QKV, launch_gemm_fp8(act8, w.w_qkv, M, 3 * C, C, EPI_QKV, ep, s), "QKV")
+    NatArgs na{};
+    const size_t plane = (size_t)H * M * 32 * 2;
+    na.q = big;
+    na.k = big + plane;
+    na.v = big + 2 * plane;
+    na.bs = T * 32;
+    na.ts = 32;
+    na.hs = (long)M * 32;
+    na.out = obuf;
+    na.obs = T * C;
+    na.ots = C;
+    na.rpb = w.rpb_log2;
+    na.qscale = 1.0f;
+    na.bscale = 1.0f;
+    na.B = B; na.Z = g.Z; na.Y = g.Y; na.X = g.X; na.H = H;
+    na.Kz = g.Kz; na.Ky = g.Ky; na.Kx = g.Kx; na.periodic = g.periodic_mask;
+    na.tbl_ws = tbl_ws;
+    WM_TIMED(PK_NA, launch_nat(na, true, s), "NA")
+    EpiArgs er{};
+    er.bias = w.b_o;
+    er.resid = x;
+    WM_TIMED(PK_PROJ, launch_gemm(obuf, w.w_o, M, C, C, true, EPI_RESID, er, s), "proj")
+    WM_TIMED(PK_LN2, launch_layernorm_fp8(x, w.ln2_g, w.ln2_b, M, C, (int)T, 1e-5f, amax_w, act8, s), "LN2")
+    EpiArgs eg{};
+    eg.bias = w.b_1;
+    eg.out = big;
+    eg.a_amax = (const float *)amax_w;
+    eg.w_dequant = w.dq_1;
+    eg.T = T;
+    eg.out_amax = amax_h;
+    eg.amax_stride = 1;
+    WM_TIMED(PK_MLP1, launch_gemm_fp8(act8, w.w_1, M, F, C, EPI_GELU, eg, s), "MLP1")
+    if ((e = launch_quant_rows(big, (size_t)M * F, F, T, (const float *)amax_h, h8, s)) != hipSuccess)
+        return hip_fail(e, "quantize h");
+    EpiArgs e2{};
+    e2.bias = w.b_2;
+    e2.resid = x;
+    e2.a_amax = (const float *)amax_h;
+    e2.w_dequant = w.dq_2;
+    e2.T = T;
+    WM_TIMED(PK_MLP2, launch_gemm_fp8(h8, w.w_2, M, C, F, EPI_RESID, e2, s), "MLP2")
+#undef WM_TIMED
+    return WM_OK;
+}
+
 int run_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, hipStream_t s) {
     for (int b = 0; b < p->nb; ++b) {
         int rc = run_block(ctx, p, b, B, x, s);
         if (rc) return rc;
     }
     return WM_OK;
+}
+
+unsigned char host_fp8_e4m3(float x) {
+    const unsigned char sign = std::signbit(x) ? 0x80 : 0x00;
+    double a = std::fabs((double)x);
+    if (std::isnan(x)) return 0x7f;
+    if (a > 448.0) a = 448.0;
+    // exponent of the representable grid around a: normals 2^-6 .. 2^8
+    int e = a > 0 ? (int)std::floor(std::log2(a)) : -6;
+    if (e < -6) e = -6;
+    double q = std::nearbyint(a / std::ldexp(1.0, e - 3));   // mantissa units, ties to even
+    if (q >= 16.0) {                                           // rounded up into the next binade
+        e += 1;
+        q = 8.0;
+    }
+    if (e > 8 || (e == 8 && q > 14.0)) {                      // saturate at 448
+        e = 8;
+        q = 14.0;
+    }
+    unsigned char code;
+    if (q < 8.0) code = (unsigned char)q;                      // subnormal (e == -6)
+    else code = (unsigned char)(((e + 7) << 3) | ((int)q - 8));
+    return sign | code;
 }
 
 // Sec. 2.1, latent rollout: the six-hour and one-hour processors are called

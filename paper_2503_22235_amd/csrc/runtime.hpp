@@ -15,6 +15,9 @@ namespace wm {
 struct BlockWeights {
     const float *ln1_g, *ln1_b, *b_qkv, *rpb_log2, *b_o, *ln2_g, *ln2_b, *b_1, *b_2;
     const void *w_qkv, *w_o, *w_1, *w_2;   // [out][in], processor precision
+    // FP8 processors: w_qkv, w_1, w_2 hold e4m3 codes with these per-tensor
+    // dequantization scales (amax / 448); w_o stays bfloat16.
+    float dq_qkv = 1.f, dq_1 = 1.f, dq_2 = 1.f;
 };
 
 constexpr int MAX_BLOCKS = 64;
@@ -63,6 +66,9 @@ int prof_end(wm_ctx *ctx, hipStream_t s);
 // Enqueue one block / one step on `s` (workspace already reserved).
 int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s);
 int run_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, hipStream_t s);
+// Host OCP e4m3 encoding, round to nearest even, saturating at +-448.
+unsigned char host_fp8_e4m3(float x);
+
 // Greedy 6 h / 1 h schedule; writes up to cap entries if out != nullptr and
 // returns the number of steps.
 int greedy_schedule(int lead_hours, int *out, int cap);

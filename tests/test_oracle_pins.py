@@ -376,3 +376,27 @@ def test_rel_l2():
     a = np.array([3.0, 4.0])
     assert O.rel_l2(a, a) == 0.0
     assert abs(O.rel_l2(np.array([3.0, 5.0]), a) - 0.2) < 1e-16
+
+
+# --------------------------------------------------------------------------
+# e4m3 codec used to check FP8 codes (OCP FP8 format definition).
+# --------------------------------------------------------------------------
+def test_e4m3_table_and_rounding():
+    v = O.e4m3_values()
+    assert v[0x7E] == 448.0 and v[0x08] == 2.0 ** -6 and v[0x01] == 2.0 ** -9
+    assert v[0x38] == 1.0 and np.isnan(v[0x7F])
+    fin = v[:127]
+    assert np.all(np.diff(fin) > 0)
+    # every finite value encodes to itself, with either sign
+    codes = np.arange(127, dtype=np.uint8)
+    assert np.array_equal(O.e4m3_encode(fin), codes)
+    assert np.array_equal(O.e4m3_encode(-fin[1:]), codes[1:] | 0x80)
+    # midpoints go to the even code; saturation at 448
+    mids = (fin[1:] + fin[:-1]) / 2
+    enc = O.e4m3_encode(mids)
+    assert np.all(enc % 2 == 0)
+    assert O.e4m3_encode(np.array([1000.0, -500.0])).tolist() == [0x7E, 0xFE]
+    assert O.e4m3_encode(np.array([2.0 ** -10])).tolist() == [0]
+    r = np.random.default_rng(0).standard_normal(10000) * 50
+    back = O.e4m3_decode(O.e4m3_encode(r))
+    assert np.all(np.abs(back - np.clip(r, -448, 448)) <= np.maximum(np.abs(r) * 2.0 ** -4, 2.0 ** -10) + 1e-12)
