@@ -2,18 +2,20 @@
 
 Workload: one processor step = 8 pre-norm neighborhood-attention blocks on a
 latent state of 8 x 90 x 180 tokens (level x lat x lon), C=512, 16 heads,
-window 5x7x7 (lon periodic, lat/level clamped), MLP ratio 4, batch 1,
-BF16 contractions with float32 accumulation and a float32 residual stream.
+window 5x7x7 (lon periodic, lat/level clamped), MLP ratio 4, batch 1, BF16
+contractions with float32 accumulation and a float32 residual stream.
 Inputs are seeded synthetic data (state N(0,1), weights N(0,0.02)) already
 resident in HBM when the timed region starts.
 
-Prints ONE JSON line.  `value` is processor-steps/s (BF16 path); the FP32
-plain path is timed on the same inputs beside it.  `roofline` is the
-dominant kernel's algorithmic rate over its average duration, measured with
-HIP events recorded on the launch stream inside the timed region.
-`cpu_baseline` times the FP64 CPU oracle on one block of the same step.
+Prints ONE JSON line.  `value` is processor-steps/s of the BF16 path.  Beside
+it: the FP32 plain path and the FP8 path (batch of 4 states) on the same
+inputs, a continuous-batching serving run with p50/p99 latency, the dominant
+kernel's roofline (its algorithmic rate over its average duration, from HIP
+events recorded on the launch stream inside the timed region), and the FP64
+CPU oracle timed on a bounded sample of the same step.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,19 +26,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "latent processor-steps/s at 8x90x180 (BF16/FP8 vs FP32); p50/p99 serve latency"
 PEAK_BF16_TFLOPS = 2500.0
-PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_8x90x180.json")
 
 
 def block_kernel_work(g, B=1, mlp=4):
-    """Algorithmic FLOPs and HBM bytes per launch of each block kernel.
+    """Algorithmic FLOPs and HBM bytes per launch of each block kernel (bf16).
 
-    Bytes: every operand read once and every result written once (bf16
-    activations, float32 residual stream, weights read once)."""
+    Bytes count every operand read once and every result written once (bf16
+    activations, float32 residual stream, weights once)."""
     T = g.Z * g.Y * g.X * B
     C, F, H = g.C, g.C * mlp, g.heads
     kvol = g.Kz * g.Ky * g.Kx
-    a = 2  # bf16 bytes
+    a = 2
     return {
         "ln1": (8.0 * T * C, T * C * 4 + T * C * a),
         "qkv": (2.0 * T * C * 3 * C, T * C * a + 3 * C * C * a + T * 3 * C * a),
@@ -54,16 +56,25 @@ def step_flops(g, nb=8, B=1, mlp=4):
     return nb * T * (2 * (3 + 1 + 2 * mlp) * g.C * g.C + 4 * g.C * kvol)
 
 
-def time_steps(wm, torch, ctx, proc, x, steps, warmup, profile=False):
+def kernel_source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2503_22235_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def time_steps(wm, torch, ctx, proc, x, B, steps, warmup, profile=False):
     for _ in range(warmup):
-        wm.wm_processor_step(ctx, proc, 1, x)
+        wm.wm_processor_step(ctx, proc, B, x)
     torch.cuda.synchronize()
     if profile:
         wm.wm_prof_collect(ctx)
         wm.wm_prof_enable(ctx, True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        wm.wm_processor_step(ctx, proc, 1, x)
+        wm.wm_processor_step(ctx, proc, B, x)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof = None
@@ -73,9 +84,61 @@ def time_steps(wm, torch, ctx, proc, x, steps, warmup, profile=False):
     return dt, prof
 
 
-def cpu_baseline(g, params):
-    """FP64 oracle on one of the step's 8 blocks over the full grid."""
+def serve_run(wm, np, S, ctx, g, p6, p1, n_req, rate, max_batch, seed=3):
+    """Poisson arrivals, leads uniform in 1..336 h, BF16 states in HBM slots."""
+    import wm_synth
+    arrivals, leads = wm_synth.serving_trace(n_req, rate, seed=seed)
+    x0 = S.latent_state(g, 1, seed=0)[0]
+    slot_bytes = g.T * g.C * 2
+    srv = wm.wm_serve_create(ctx, p6, p1, max_batch=max_batch, state_bf16=True,
+                             hbm_budget_bytes=12 * slot_bytes)
+    slots = wm.wm_serve_status(srv)["slots"]
+    pending, stats = {}, []
+    out = np.empty(x0.shape, np.float32)
+    t0 = time.perf_counter()
+    nxt = 0
+    while nxt < n_req or pending:
+        now = time.perf_counter() - t0
+        while nxt < n_req and arrivals[nxt] <= now:
+            rid = wm.wm_serve_submit(srv, x0, int(leads[nxt]))
+            pending[rid] = nxt
+            nxt += 1
+        for rid in list(pending):
+            ok, st = wm.wm_serve_poll(srv, rid, out)
+            if ok:
+                stats.append(st)
+                del pending[rid]
+        time.sleep(0.002)
+    srv.close()
+    lat = np.array([s["t_done"] - s["t_submit"] for s in stats])
+    steps = sum(s["steps"] for s in stats)
+    span = max(s["t_done"] for s in stats) - min(s["t_submit"] for s in stats)
+    batches = sum(s["batches"] for s in stats)
+    return {"requests": n_req, "rate_per_s": round(rate, 3), "max_batch": max_batch, "slots": slots,
+            "leads_h": "uniform 1..336", "state": "bf16 in HBM",
+            "steps_per_s": round(steps / span, 2), "requests_per_s": round(n_req / span, 3),
+            "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+            "mean_steps": round(steps / n_req, 2), "arrivals": arrivals, "leads": leads,
+            "_batches": batches}
+
+
+def fifo_model(arrivals, leads, step_s):
+    """Latencies of the same arrival trace through one FIFO server that runs
+    each request alone at step_s seconds per processor step."""
     import numpy as np
+    from oracle import wm_oracle as O
+    free, lat = 0.0, []
+    for a, L in zip(arrivals, leads):
+        start = max(a, free)
+        free = start + len(O.schedule(int(L))) * step_s
+        lat.append(free - a)
+    lat = np.array(lat)
+    return {"p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+            "kind": "FIFO replay of the same arrivals at the measured FP32 step time"}
+
+
+def cpu_baseline(g, params, nblocks=2):
+    """FP64 oracle on the first blocks of the step over the full grid."""
     import wm_synth as S
     from oracle import build_oracle
     from oracle import wm_oracle as O
@@ -84,19 +147,18 @@ def cpu_baseline(g, params):
     threads = O.oracle_threads()
     try:
         from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(limits=threads)
+        ctxm = threadpool_limits(limits=threads)
     except Exception:
-        limiter = None
+        ctxm = None
     x = S.latent_state(g, 1, seed=0)
     t0 = time.perf_counter()
-    O.block(x, S.split_block_params(g, params, 0), g)
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.unregister() if hasattr(limiter, "unregister") else None
-    return {"value": 1.0 / (8 * dt), "unit": "processor-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"1 of the 8 blocks of one step, full 8x90x180 grid, FP64 "
-                      f"({dt:.1f} s); steps/s = 1/(8 x block time)"}
+    for b in range(nblocks):
+        x = O.block(x, S.split_block_params(g, params, b), g)
+    dt = (time.perf_counter() - t0) / nblocks
+    del ctxm
+    return {"value": round(1.0 / (8 * dt), 5), "unit": "processor-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nblocks} of the 8 blocks of one step on the full 8x90x180 grid, FP64 "
+                      f"({dt:.1f} s per block); steps/s = 1/(8 x block time)"}
 
 
 def main():
@@ -104,12 +166,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-fp8", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no "
-              "multi-GPU mode", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the processor step is measured "
+              "on one GPU's share and no multi-GPU mode exists", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -120,17 +185,19 @@ def main():
     if not os.path.exists(wm.LIB_PATH):
         from paper_2503_22235_amd import build
         build.build()
+    log = lambda m: print("bench: " + m, file=sys.stderr, flush=True)
     g = S.CFG2
     nb = 8
-    print(f"bench: generating inputs {g}", file=sys.stderr, flush=True)
-    params = S.processor_params(g, nb, seed=1)
-    x0 = S.latent_state(g, 1, seed=0)
+    log(f"generating inputs {g}")
+    params6 = S.processor_params(g, nb, seed=1, proc=0)
+    x0 = S.latent_state(g, 4, seed=0)
     ctx = wm.wm_ctx_create(0)
-    x = torch.from_numpy(x0).cuda()
+    x = torch.from_numpy(x0[:1].copy()).cuda()
 
-    p_bf = wm.wm_processor_create(ctx, g, nb, 4, wm.WM_BF16, params)
-    print("bench: bf16 timed region", file=sys.stderr, flush=True)
-    dt, prof = time_steps(wm, torch, ctx, p_bf, x, args.steps, args.warmup, profile=True)
+    # ---- BF16, batch 1: the headline --------------------------------------
+    p_bf = wm.wm_processor_create(ctx, g, nb, 4, wm.WM_BF16, params6)
+    log("bf16 timed region")
+    dt, prof = time_steps(wm, torch, ctx, p_bf, x, 1, args.steps, args.warmup, profile=True)
     sps = args.steps / dt
     work = block_kernel_work(g)
     per_kernel = {}
@@ -143,41 +210,74 @@ def main():
                              "gbs": round(by / (avg * 1e-3) / 1e9, 1)}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
     d = per_kernel[dom]
-    if dom in ("qkv", "proj", "mlp1", "mlp2", "nat"):
-        roof = {"kernel": dom, "bound": "mfma", "achieved": d["tflops"], "peak": PEAK_BF16_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_BF16_TFLOPS, 4), "traffic": None}
+    if dom in ("ln1", "ln2"):
+        roof = {"kernel": dom, "bound": "hbm", "achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(d["gbs"] / PEAK_HBM_GBS, 4)}
     else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": d["gbs"], "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(d["gbs"] / PEAK_HBM_GBS, 4), "traffic": None}
-
-    fp32 = None
-    if not args.no_fp32:
-        p_bf.close()
-        p32 = wm.wm_processor_create(ctx, g, nb, 4, wm.WM_F32, params)
-        print("bench: fp32 timed region", file=sys.stderr, flush=True)
-        x.copy_(torch.from_numpy(x0))
-        k32 = max(2, args.steps // 4)
-        dt32, _ = time_steps(wm, torch, ctx, p32, x, k32, 1)
-        fp32 = {"steps_per_s": round(k32 / dt32, 3), "ms_per_step": round(dt32 / k32 * 1e3, 2),
-                "steps": k32}
-        p32.close()
+        roof = {"kernel": dom, "bound": "mfma", "achieved": d["tflops"], "peak": PEAK_BF16_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_BF16_TFLOPS, 4)}
+    roof["traffic"] = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("kernels", {}):
+            roof["traffic"] = tr["kernels"][dom]["hbm_bytes_per_launch"]
     flops = step_flops(g, nb)
     out = {
         "metric": METRIC, "value": round(sps, 3), "unit": "processor-steps/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(dt / args.steps * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
-        "config": {"workload": "latent processor step, 8 blocks, 8x90x180 latent, C=512, "
-                               "16 heads, window 5x7x7 (lon periodic), MLP ratio 4, B=1",
+        "config": {"workload": "latent processor step, 8 blocks, 8x90x180 latent, C=512, 16 heads, "
+                               "window 5x7x7 (lon periodic), MLP ratio 4, B=1",
                    "global_batch": 1, "tokens": g.T, "parallelism": "single-gpu"},
         "roofline": roof,
         "step_mfma_frac": round(flops * sps / (PEAK_BF16_TFLOPS * 1e12), 4),
         "kernels": per_kernel,
-        "fp32_plain": fp32,
     }
+
+    # ---- serving (bf16 processors for 6 h and 1 h) -----------------------
+    if not args.no_serve and args.serve_requests > 0:
+        p1_bf = wm.wm_processor_create(ctx, g, nb, 4, wm.WM_BF16, S.processor_params(g, nb, seed=2, proc=1))
+        rate = 0.7 * sps / 30.17
+        log(f"serving run: {args.serve_requests} requests at {rate:.2f}/s")
+        sv = serve_run(wm, np, S, ctx, g, p_bf, p1_bf, args.serve_requests, rate, max_batch=8)
+        p1_bf.close()
+        out["serve"] = {k: v for k, v in sv.items() if not k.startswith("_") and k not in ("arrivals", "leads")}
+        out["_serve_trace"] = (sv["arrivals"], sv["leads"])
+    p_bf.close()
+
+    # ---- FP32 plain path, batch 1 -----------------------------------------
+    if not args.no_fp32:
+        p32 = wm.wm_processor_create(ctx, g, nb, 4, wm.WM_F32, params6)
+        log("fp32 timed region")
+        x.copy_(torch.from_numpy(x0[:1].copy()))
+        k32 = max(2, args.steps // 4)
+        dt32, _ = time_steps(wm, torch, ctx, p32, x, 1, k32, 1)
+        out["fp32_plain"] = {"steps_per_s": round(k32 / dt32, 3), "ms_per_step": round(dt32 / k32 * 1e3, 2),
+                             "steps": k32}
+        p32.close()
+        if "_serve_trace" in out:
+            arr, leads = out["_serve_trace"]
+            out["serve"]["fp32_one_at_a_time"] = fifo_model(arr, leads, dt32 / k32)
+    out.pop("_serve_trace", None)
+
+    # ---- FP8, batch of 4 states -------------------------------------------
+    if not args.no_fp8:
+        p8 = wm.wm_processor_create(ctx, g, nb, 4, wm.WM_FP8_E4M3, params6)
+        log("fp8 timed region (4 states)")
+        x4 = torch.from_numpy(x0).cuda()
+        k8 = max(2, args.steps // 2)
+        dt8, _ = time_steps(wm, torch, ctx, p8, x4, 4, k8, 1)
+        xb = torch.from_numpy(x0[:1].copy()).cuda()
+        dt81, _ = time_steps(wm, torch, ctx, p8, xb, 1, k8, 1)
+        out["fp8"] = {"batch": 4, "state_steps_per_s": round(4 * k8 / dt8, 3),
+                      "ms_per_batch_step": round(dt8 / k8 * 1e3, 2),
+                      "b1_steps_per_s": round(k8 / dt81, 3)}
+        p8.close()
+
     if not args.no_cpu_baseline:
-        print("bench: cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(g, params)
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(g, params6)
     ctx.close()
     print(json.dumps(out), flush=True)
 
