@@ -84,9 +84,9 @@ void wm_ctx_destroy(wm_ctx *ctx);
  * bracketed by HIP events recorded on the stream it is launched on.
  * wm_prof_collect waits for the recorded events, ADDS each kernel kind's
  * total milliseconds and launch count into ms[kind] and counts[kind]
- * (kinds 0..6: LN1, QKV projection, neighborhood attention, output
- * projection, LN2, MLP1, MLP2; arrays of nkinds entries, either may be
- * NULL) and clears the records. */
+ * (kinds 0..7: LN1, QKV projection, neighborhood attention, output
+ * projection, LN2, MLP1, MLP2, FP8 quantization of the MLP hidden state;
+ * arrays of nkinds entries, either may be NULL) and clears the records. */
 int wm_prof_enable(wm_ctx *ctx, int on);
 int wm_prof_collect(wm_ctx *ctx, double *ms, long long *counts, int nkinds);
 

@@ -4,7 +4,9 @@
 //   s = amax / 448   (amax = max |value| over the state's tokens),
 // and codes q = RNE(clamp(value * (448 / amax), -448, 448)).  amax values
 // are kept as float bits and combined with unsigned atomicMax (|v| >= 0, so
-// the bit patterns order like the values).
+// the bit patterns order like the values).  Producers spread their atomics
+// over AMAX_SHARDS copies of each slot (shard = workgroup id mod shards);
+// amax_fold then reduces the copies into shard 0, which consumers read.
 #include "kernels.hpp"
 
 namespace wm {
@@ -54,7 +56,16 @@ __global__ __launch_bounds__(256) void ln_amax_kernel(const float *__restrict__ 
             m = fmaxf(m, fabsf((v[2 * j + u] - mean) * rstd * gamma[c] + beta[c]));
         }
     m = wave_max(m);
-    if (lane == 0) atomicMax(amax + row / T, __float_as_uint(m));
+    if (lane == 0) atomicMax(amax + (blockIdx.x % AMAX_SHARDS) * AMAX_STRIDE + row / T, __float_as_uint(m));
+}
+
+// Fold the shard copies of n amax slots into shard 0.
+__global__ void amax_fold_kernel(unsigned *amax, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned m = 0;
+    for (int s = 0; s < AMAX_SHARDS; ++s) m = max(m, amax[s * AMAX_STRIDE + i]);
+    amax[i] = m;
 }
 
 // Pass 2: LayerNorm, then quantize with the state's scale.
@@ -95,20 +106,30 @@ __global__ __launch_bounds__(256) void ln_quant_kernel(const float *__restrict__
     }
 }
 
-// bf16 [B*T][F] -> e4m3 with the scale of each row's state.
-__global__ __launch_bounds__(256) void quant_rows_kernel(const bf16 *__restrict__ in, size_t n4, int F, long T,
+// bf16 rows [M][F] -> e4m3 with the scale of each row's state.  One wave per
+// row (the state is looked up once), 8 values per lane per step.
+__global__ __launch_bounds__(256) void quant_rows_kernel(const bf16 *__restrict__ in, int M, int F, int T,
                                                          const float *__restrict__ amax,
                                                          unsigned char *__restrict__ out) {
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (size_t)gridDim.x * 256) {
-        const size_t e = 4 * i;
-        const long row = (long)(e / F);
-        const float inv = inv_scale(amax[row / T]);
-        const uint2 u = *(const uint2 *)(in + e);
-        const float a = bf_bits2f((unsigned short)(u.x & 0xffff)) * inv;
-        const float b = bf_bits2f((unsigned short)(u.x >> 16)) * inv;
-        const float c = bf_bits2f((unsigned short)(u.y & 0xffff)) * inv;
-        const float d = bf_bits2f((unsigned short)(u.y >> 16)) * inv;
-        *(unsigned *)(out + e) = pack4_fp8(a, b, c, d);
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= M) return;
+    const int lane = threadIdx.x & 63;
+    const float inv = inv_scale(amax[row / T]);
+    const bf16 *src = in + (size_t)row * F;
+    unsigned char *dst = out + (size_t)row * F;
+    for (int c = 8 * lane; c < F; c += 512) {
+        const uint4 u = *(const uint4 *)(src + c);
+        const unsigned w[4] = {u.x, u.y, u.z, u.w};
+        float f[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f[2 * q] = bf_bits2f((unsigned short)(w[q] & 0xffff)) * inv;
+            f[2 * q + 1] = bf_bits2f((unsigned short)(w[q] >> 16)) * inv;
+        }
+        uint2 o;
+        o.x = pack4_fp8(f[0], f[1], f[2], f[3]);
+        o.y = pack4_fp8(f[4], f[5], f[6], f[7]);
+        *(uint2 *)(dst + c) = o;
     }
 }
 
@@ -125,7 +146,9 @@ template <int VPT>
 hipError_t ln_fp8(const float *x, const float *g, const float *b, int M, int T, float eps, unsigned *amax,
                   unsigned char *out, hipStream_t s) {
     const int grid = (M + 3) / 4;
+    const int nstates = (M + T - 1) / T;
     ln_amax_kernel<VPT><<<grid, 256, 0, s>>>(x, g, b, M, T, eps, amax);
+    amax_fold_kernel<<<(nstates + 255) / 256, 256, 0, s>>>(amax, nstates);
     ln_quant_kernel<VPT><<<grid, 256, 0, s>>>(x, g, b, M, T, eps, (const float *)amax, out);
     return hipGetLastError();
 }
@@ -144,12 +167,16 @@ hipError_t launch_layernorm_fp8(const float *x, const float *gamma, const float 
     }
 }
 
-hipError_t launch_quant_rows(const void *in_bf16, size_t n, int F, long T, const float *amax, unsigned char *out,
+hipError_t launch_quant_rows(const void *in_bf16, int M, int F, int T, const float *amax, unsigned char *out,
                              hipStream_t stream) {
-    if (n == 0) return hipSuccess;
-    size_t blocks = (n / 4 + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    quant_rows_kernel<<<(unsigned)blocks, 256, 0, stream>>>((const bf16 *)in_bf16, n / 4, F, T, amax, out);
+    if (M <= 0) return hipSuccess;
+    if (F % 8) return hipErrorInvalidValue;
+    quant_rows_kernel<<<(M + 3) / 4, 256, 0, stream>>>((const bf16 *)in_bf16, M, F, T, amax, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_amax_fold(unsigned *amax, int n, hipStream_t stream) {
+    amax_fold_kernel<<<(n + 255) / 256, 256, 0, stream>>>(amax, n);
     return hipGetLastError();
 }
 

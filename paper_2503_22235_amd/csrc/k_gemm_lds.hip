@@ -242,16 +242,19 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
                 if (ep.out_amax) {
                     if (srow[i] == s_lo) mlo = fmaxf(mlo, a);
                     else if (srow[i] == s_lo + 1) mhi = fmaxf(mhi, a);
-                    else if (m < M) atomicMax(ep.out_amax + srow[i] * ep.amax_stride + part, __float_as_uint(a));
+                    else if (m < M)
+                        atomicMax(ep.out_amax + (blockIdx.x % AMAX_SHARDS) * AMAX_STRIDE + srow[i] * ep.amax_stride + part,
+                                  __float_as_uint(a));
                 }
             }
         if (ep.out_amax) {
             mlo = wave_max(mlo);
             mhi = wave_max(mhi);
             if (lane == 0) {
-                atomicMax(ep.out_amax + s_lo * ep.amax_stride + part, __float_as_uint(mlo));
+                unsigned *sh = ep.out_amax + (blockIdx.x % AMAX_SHARDS) * AMAX_STRIDE;
+                atomicMax(sh + s_lo * ep.amax_stride + part, __float_as_uint(mlo));
                 if ((long)(s_lo + 1) * ep.T < M)
-                    atomicMax(ep.out_amax + (s_lo + 1) * ep.amax_stride + part, __float_as_uint(mhi));
+                    atomicMax(sh + (s_lo + 1) * ep.amax_stride + part, __float_as_uint(mhi));
             }
         }
     }

@@ -53,12 +53,17 @@ hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, Ep
                            const EpiArgs &ep, hipStream_t stream);
 
 // --- FP8 quantization (OCP e4m3; per-state scale amax / 448) --------------
+// amax slots live in AMAX_SHARDS copies AMAX_STRIDE apart; producers write
+// any copy, launch_amax_fold reduces slots [0, n) into copy 0.
+constexpr int AMAX_SHARDS = 64;
+constexpr int AMAX_STRIDE = 512;            // slots per copy (>= 8 per state x 64 states)
+hipError_t launch_amax_fold(unsigned *amax, int n, hipStream_t stream);
 // Two-pass LayerNorm: per-state amax of the LN output (atomicMax into
 // amax[state], which the caller zeroes), then LN + quantize.
 hipError_t launch_layernorm_fp8(const float *x, const float *gamma, const float *beta, int M, int C, int T,
                                 float eps, unsigned *amax, unsigned char *out, hipStream_t stream);
-// bf16 rows [M][F] -> e4m3 with each row's state scale (n % 4 == 0, F % 4 == 0)
-hipError_t launch_quant_rows(const void *in_bf16, size_t n, int F, long T, const float *amax,
+// bf16 rows [M][F] -> e4m3 with each row's state scale (F % 8 == 0)
+hipError_t launch_quant_rows(const void *in_bf16, int M, int F, int T, const float *amax,
                              unsigned char *out, hipStream_t stream);
 // float32 -> e4m3 codes = RNE(clamp(x * mul, +-448))
 hipError_t launch_quant_f32(const float *in, size_t n, float mul, unsigned char *out, hipStream_t stream);

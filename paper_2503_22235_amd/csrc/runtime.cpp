@@ -15,7 +15,7 @@ size_t block_workspace_bytes(const wm_processor *p, int B) {
     if (p->prec == WM_FP8_E4M3) {
         // u8/w8 | qkv or h (bf16) | o (bf16) | h8 | bias tables | amax slots
         return al256(M * C) + al256(M * std::max(3 * C, F) * 2) + al256(M * C * 2) + al256(M * F) +
-               (size_t)p->g.heads * NAT_TBL_WS_FLOATS * 4 + al256((size_t)B * 8 * 4);
+               (size_t)p->g.heads * NAT_TBL_WS_FLOATS * 4 + (size_t)AMAX_SHARDS * AMAX_STRIDE * 4;
     }
     const size_t esz = p->prec == WM_BF16 ? 2 : 4;
     const size_t big = (3 * C > F ? 3 * C : F);
@@ -152,7 +152,9 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     if ((rc = prof_begin(ctx, s, kind)) != WM_OK) return rc;        \
     if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
     if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
-    if ((e = hipMemsetAsync(amax, 0, (size_t)B * 8 * 4, s)) != hipSuccess) return hip_fail(e, "amax reset");
+    if (B > 64) return fail(WM_EINVAL, "FP8 processors take at most 64 states per call");
+    if ((e = hipMemsetAsync(amax, 0, (size_t)AMAX_SHARDS * AMAX_STRIDE * 4, s)) != hipSuccess)
+        return hip_fail(e, "amax reset");
     WM_TIMED(PK_LN1, launch_layernorm_fp8(x, w.ln1_g, w.ln1_b, M, C, (int)T, 1e-5f, amax_u, act8, s), "LN1")
     EpiArgs ep{};
     ep.bias = w.b_qkv;
@@ -166,6 +168,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     ep.out_amax = amax_qkv;
     ep.amax_stride = 3;
     WM_TIMED(PK_QKV, launch_gemm_fp8(act8, w.w_qkv, M, 3 * C, C, EPI_QKV, ep, s), "QKV")
+    if ((e = launch_amax_fold(amax_qkv, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
     NatArgs na{};
     const size_t plane = (size_t)H * M * 32 * 2;
     na.q = big;
@@ -198,8 +201,8 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     eg.out_amax = amax_h;
     eg.amax_stride = 1;
     WM_TIMED(PK_MLP1, launch_gemm_fp8(act8, w.w_1, M, F, C, EPI_GELU, eg, s), "MLP1")
-    if ((e = launch_quant_rows(big, (size_t)M * F, F, T, (const float *)amax_h, h8, s)) != hipSuccess)
-        return hip_fail(e, "quantize h");
+    if ((e = launch_amax_fold(amax_h, B, s)) != hipSuccess) return hip_fail(e, "amax fold");
+    WM_TIMED(PK_QUANT, launch_quant_rows(big, M, F, (int)T, (const float *)amax_h, h8, s), "quantize h")
     EpiArgs e2{};
     e2.bias = w.b_2;
     e2.resid = x;

@@ -23,7 +23,7 @@ struct BlockWeights {
 constexpr int MAX_BLOCKS = 64;
 
 // Kernel kinds of a block, in launch order (timing records).
-enum ProfKind : int { PK_LN1 = 0, PK_QKV, PK_NA, PK_PROJ, PK_LN2, PK_MLP1, PK_MLP2, PK_N };
+enum ProfKind : int { PK_LN1 = 0, PK_QKV, PK_NA, PK_PROJ, PK_LN2, PK_MLP1, PK_MLP2, PK_QUANT, PK_N };
 
 struct ProfRec {
     int kind;
