@@ -122,15 +122,14 @@ def serve_run(wm, np, S, ctx, g, p6, p1, n_req, rate, max_batch, seed=3):
             "_batches": batches}
 
 
-def fifo_model(arrivals, leads, step_s):
+def fifo_model(wm, arrivals, leads, step_s):
     """Latencies of the same arrival trace through one FIFO server that runs
     each request alone at step_s seconds per processor step."""
     import numpy as np
-    from oracle import wm_oracle as O
     free, lat = 0.0, []
     for a, L in zip(arrivals, leads):
         start = max(a, free)
-        free = start + len(O.schedule(int(L))) * step_s
+        free = start + len(wm.wm_schedule(int(L))) * step_s
         lat.append(free - a)
     lat = np.array(lat)
     return {"p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
@@ -161,6 +160,90 @@ def cpu_baseline(g, params, nblocks=2):
                       f"({dt:.1f} s per block); steps/s = 1/(8 x block time)"}
 
 
+KIND_ORDER = ("ln1", "qkv", "nat", "proj", "ln2", "mlp1", "mlp2")
+
+
+def _counter_rows(d, counter):
+    """(dispatch id, kernel name, value) of one counter from a rocprofv3 --pmc run."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {d}")
+    return rows
+
+
+def _per_kind(rows):
+    """Sum a counter per block-kernel launch, launches identified by their
+    order inside a block: LN, GEMM, attention (bias prep + tile kernel), GEMM,
+    LN, GEMM, GEMM."""
+    want = {"ln1": "ln", "qkv": "gemm", "nat": "nat", "proj": "gemm", "ln2": "ln", "mlp1": "gemm", "mlp2": "gemm"}
+    launches = []
+    for _, name, v in rows:
+        if "wm::" not in name:
+            continue
+        t = "ln" if "layernorm" in name else "gemm" if "gemm" in name else "nat" if "nat" in name else None
+        if t is None:
+            raise SystemExit(f"unexpected library kernel {name}")
+        if t == "nat" and launches and launches[-1][0] == "nat" and "bias_prep" not in name:
+            launches[-1][1] += v
+        else:
+            launches.append([t, v])
+    if len(launches) % 7:
+        raise SystemExit(f"{len(launches)} launches is not a whole number of blocks")
+    acc = {k: [] for k in KIND_ORDER}
+    for i, (t, v) in enumerate(launches):
+        k = KIND_ORDER[i % 7]
+        if want[k] != t:
+            raise SystemExit(f"launch {i}: expected {want[k]}, found {t}")
+        acc[k].append(v)
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic_from(fetch_dir, write_dir, copy_mib):
+    """HBM bytes per launch of each block kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, then WRITE_SIZE; both in KiB per dispatch), each scaled by
+    the reading of the same counter for a plain copy kernel of known size."""
+    g_ = __import__("wm_synth").CFG2
+    f_rows, w_rows = _counter_rows(fetch_dir, "FETCH_SIZE"), _counter_rows(write_dir, "WRITE_SIZE")
+    known_kib = copy_mib * 1024.0
+    cf = [v for _, n, v in f_rows if "neg" in n]
+    cw = [v for _, n, v in w_rows if "neg" in n]
+    if not cf or not cw:
+        raise SystemExit("copy probe dispatches not found")
+    ff, fw = (sum(cf) / len(cf)) / known_kib, (sum(cw) / len(cw)) / known_kib
+    fk, wk = _per_kind(f_rows), _per_kind(w_rows)
+    work = block_kernel_work(g_)
+    kern = {}
+    for k in KIND_ORDER:
+        rb, wb = fk[k] * 1024.0 / ff, wk[k] * 1024.0 / fw
+        kern[k] = {"fetch_bytes": round(rb), "write_bytes": round(wb), "hbm_bytes_per_launch": round(rb + wb),
+                   "algorithmic_bytes": work[k][1], "ratio": round((rb + wb) / work[k][1], 3)}
+    out = {"workload": "8x90x180, C=512, 16 heads, window 5x7x7, B=1, bf16 processor",
+           "source_hash": kernel_source_hash(),
+           "copy_probe": {"mib_read": copy_mib, "mib_written": copy_mib,
+                          "fetch_factor": round(ff, 4), "write_factor": round(fw, 4)},
+           "kernels": kern}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+def copy_probe(torch, mib):
+    """A plain elementwise copy of known size (mib MiB read, mib MiB written)."""
+    a = torch.ones(mib * 262144, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,7 +254,14 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run a plain copy of this many MiB (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic file from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(args.traffic_from[0], args.traffic_from[1], args.copy_probe_mib or 1024)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the processor step is measured "
               "on one GPU's share and no multi-GPU mode exists", file=sys.stderr)
@@ -235,6 +325,9 @@ def main():
         "kernels": per_kernel,
     }
 
+    if args.copy_probe_mib:
+        copy_probe(torch, args.copy_probe_mib)
+
     # ---- serving (bf16 processors for 6 h and 1 h) -----------------------
     if not args.no_serve and args.serve_requests > 0:
         p1_bf = wm.wm_processor_create(ctx, g, nb, 4, wm.WM_BF16, S.processor_params(g, nb, seed=2, proc=1))
@@ -258,7 +351,7 @@ def main():
         p32.close()
         if "_serve_trace" in out:
             arr, leads = out["_serve_trace"]
-            out["serve"]["fp32_one_at_a_time"] = fifo_model(arr, leads, dt32 / k32)
+            out["serve"]["fp32_one_at_a_time"] = fifo_model(wm, arr, leads, dt32 / k32)
     out.pop("_serve_trace", None)
 
     # ---- FP8, batch of 4 states -------------------------------------------
