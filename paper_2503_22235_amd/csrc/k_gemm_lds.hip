@@ -1,23 +1,24 @@
-// bf16 MFMA GEMM with a 3-stage LDS ring filled by direct buffer->LDS loads.
+// MFMA GEMM (bf16 or e4m3 operands, float32 accumulation) fed by an LDS
+// ring that direct buffer->LDS loads fill.
 //
 //   D[m][n] = sum_k A[m][k] * W[n][k]      (A: tokens x K, W: [out][in])
 //
-// Workgroup = 256 threads (4 waves, 2 x 2), tile BM x BN (128 x 128 by
-// default: wave tile 64 x 64, 4 x 4 MFMA 16x16x32 tiles, 16 MFMA per
-// 32-wide k-step against 8 fragment reads; 256 x 128 also built).  K
-// advances in 64-element (128-byte) stages.
-// A workgroup owns one token tile and walks several output-feature tiles;
-// the stage stream runs on across tile boundaries, so the next tile's first
-// loads are in flight while the previous tile's epilogue runs.
+// A workgroup of WGM x WGN waves computes a BM x BN tile; each wave owns a
+// (BM/WGM) x (BN/WGN) sub-tile of 16x16x32 MFMA tiles.  The default for the
+// block's shapes is 256 x 256 with 8 waves (wave tile 64 x 128) and two
+// 64 KB stages, one workgroup per CU; 128 x 128 with 4 waves and two
+// workgroups per CU covers N not divisible by 256.  K advances in stages of
+// BKB bytes per row (64 bf16 or 128 e4m3 values for 128-byte rows).
 // Each stage is written straight from global memory into LDS by
 // buffer_load_dwordx4 ... lds (no register staging), issued STAGES-1
-// stages ahead; with two stages (64 KB) two workgroups share a CU and hide
-// each other's load latency and epilogues.  Rows of
-// A past M come back as zeros from the buffer range check, which handles
-// the ragged last token tile.  LDS rows are 128 bytes; their 16-byte chunks
-// are XOR-swizzled by (row >> 1) & 7 so the 16 rows a fragment read touches
-// fall in distinct banks.  The MFMA "A" operand is the weight tile and "B"
-// the activation tile, so every lane ends up with four consecutive output
+// stages ahead.  A workgroup owns one token tile and walks one or more
+// output-feature tiles; the stage stream runs on across tile boundaries, so
+// the next tile's first loads are in flight while the previous tile's
+// epilogue runs.  Rows of A past M come back as zeros from the buffer range
+// check, which handles the ragged last token tile.  16-byte chunks of an LDS
+// row are XOR-swizzled so the 16 rows one fragment read touches fall in
+// distinct banks.  The MFMA "A" operand is the weight tile and "B" the
+// activation tile, so every lane ends up with four consecutive output
 // features of one token for the epilogue.  Tiles go out in an XCD-aware
 // order (consecutive ids on one XCD share an activation tile in its L2).
 #include <cstdlib>
@@ -27,12 +28,15 @@
 namespace wm {
 namespace glds {
 
-constexpr int NT = 256;
-constexpr int BK_BYTES = 128;
-
 typedef __attribute__((address_space(3))) void lds_void;
 
-__device__ __forceinline__ int swz(int row) { return (row >> 1) & 7; }
+// XOR swizzle of the 16-byte chunks of an LDS row of BKB bytes: 128-byte rows
+// by (row >> 1) & 7, 64-byte rows by (row >> 2) & 3, so the 16 rows that one
+// fragment read touches fall in distinct banks.
+template <int BKB>
+__device__ __forceinline__ int swz(int row) {
+    return BKB == 128 ? (row >> 1) & 7 : (row >> 2) & 3;
+}
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, unsigned bytes) {
     const unsigned long long v = (unsigned long long)p;
@@ -88,18 +92,36 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// Wait until at most `rem` (clipped to MAXN) later stages' loads are
+// outstanding: rem is the number of stages issued after the one needed.
+template <int MAXN, int LPW>
+__device__ __forceinline__ void wait_stages(int rem) {
+    if constexpr (MAXN == 0) {
+        wait_vmcnt<0>();
+    } else {
+        if (rem >= MAXN) wait_vmcnt<MAXN * LPW>();
+        else wait_stages<MAXN - 1, LPW>(rem);
+    }
+}
+
 // FP8: operands are e4m3 bytes (128 k-values per 128-byte stage, MFMA
 // 16x16x32 fp8 with 8-byte fragments); the epilogue dequantizes per row.
-template <int BM, int BN, int STAGES, int EPI, bool FP8>
-__global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const void *__restrict__ A, const void *__restrict__ W,
+// WGM x WGN waves tile the BM x BN output; OCC workgroups share a CU.
+template <int BM, int BN, int BKB, int STAGES, int WGM, int WGN, int OCC, int EPI, bool FP8>
+__global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const void *__restrict__ A, const void *__restrict__ W,
                                                          int M, int N, int K, EpiArgs ep, int tpw) {
 #if defined(__HIP_DEVICE_COMPILE__)   // LDS-address-space builtins exist only in the device pass
-    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int NW = WGM * WGN;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int ROWS = BM + BN;                  // LDS rows per stage
-    constexpr int STAGE_BYTES = ROWS * BK_BYTES;
-    constexpr int LPW = ROWS / 8 / 4;              // load instructions per wave per stage
-    static_assert(ROWS % 32 == 0 && BM % 32 == 0, "rows per stage must split over 4 waves x 8 rows");
+    constexpr int STAGE_BYTES = ROWS * BKB;
+    constexpr int CPR = BKB / 16;                  // 16-byte chunks per LDS row
+    constexpr int RPI = 64 / CPR;                  // rows one load instruction fills
+    constexpr int LPW = ROWS / RPI / NW;           // load instructions per wave per stage
+    static_assert(BKB == 128 || BKB == 64, "stage row bytes");
+    static_assert(ROWS % (RPI * NW) == 0 && BM % (RPI * NW) == 0, "rows per stage must split over the waves");
+    static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile");
     extern __shared__ __align__(16) unsigned char smem[];
 
     const int ntn = N / BN, ntm = (M + BM - 1) / BM;
@@ -114,34 +136,35 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
     const int nn = min(tpw, ntn - tn0);          // output-feature tiles of this workgroup
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % WGM, wn = wave / WGM;
     const int g = lane >> 4, r16 = lane & 15;
     const unsigned Kb = (unsigned)K * (FP8 ? 1 : 2);
     const __amdgpu_buffer_rsrc_t ars = make_rsrc(A, (unsigned)M * Kb);
     const __amdgpu_buffer_rsrc_t wrs = make_rsrc(W, (unsigned)N * Kb);
 
     // per-lane global byte offsets of this wave's load instructions
-    // Instruction i of wave w fills LDS rows 8(w + 4i) .. +7; since BM is a
-    // multiple of 32, rows below BM (activation rows) are exactly i < BM/32.
+    // Instruction i of wave w fills LDS rows RPI(w + NW i) .. +RPI-1; since BM
+    // is a multiple of RPI NW, rows below BM (activation rows) are exactly
+    // i < BM/(RPI NW).
     unsigned voff[LPW];
 #pragma unroll
     for (int i = 0; i < LPW; ++i) {
-        const int row = 8 * (wave + 4 * i) + (lane >> 3);
-        const int lc = (lane & 7) ^ swz(row);
-        voff[i] = i < BM / 32 ? (unsigned)(m0 + row) * Kb + lc * 16
+        const int row = RPI * (wave + NW * i) + lane / CPR;
+        const int lc = (lane % CPR) ^ swz<BKB>(row);
+        voff[i] = i < BM / (RPI * NW) ? (unsigned)(m0 + row) * Kb + lc * 16
                               : (unsigned)(tn0 * BN + row - BM) * Kb + lc * 16;
     }
-    const int nk = K / (FP8 ? 128 : 64);
+    const int nk = K / (FP8 ? BKB : BKB / 2);
     // stage s of the stream = k-stage (s % nk) of feature tile (s / nk)
     auto issue = [&](int s, int stage) {
         const int t = s / nk, kt = s - t * nk;
         unsigned char *sbase = smem + stage * STAGE_BYTES;
-        const unsigned wsoff = (unsigned)t * BN * Kb + kt * BK_BYTES;
+        const unsigned wsoff = (unsigned)t * BN * Kb + kt * BKB;
 #pragma unroll
         for (int i = 0; i < LPW; ++i) {
-            lds_void *dst = (lds_void *)(sbase + 8 * (wave + 4 * i) * BK_BYTES);
-            if (i < BM / 32)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(ars, dst, 16, voff[i], kt * BK_BYTES, 0, 0);
+            lds_void *dst = (lds_void *)(sbase + RPI * (wave + NW * i) * BKB);
+            if (i < BM / (RPI * NW))
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ars, dst, 16, voff[i], kt * BKB, 0, 0);
             else
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, dst, 16, voff[i], wsoff, 0, 0);
         }
@@ -156,14 +179,14 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
     // lane-constant fragment offsets inside a stage (swizzle depends on r16
     // only): bf16 k-step ks reads 16 bytes at k = 32ks + 8g; fp8 k-step ks
     // reads 8 bytes at k = 32ks + 8g.
-    constexpr int KSTEPS = FP8 ? 4 : 2;
+    constexpr int KSTEPS = FP8 ? BKB / 32 : BKB / 64;
     int aoff[KSTEPS], woff[KSTEPS];
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
-        const int pc = FP8 ? ((((2 * ks + (g >> 1)) ^ ((r16 >> 1) & 7)) << 4) + 8 * (g & 1))
-                           : (((4 * ks + g) ^ ((r16 >> 1) & 7)) << 4);
-        aoff[ks] = (wm * WM + r16) * BK_BYTES + pc;
-        woff[ks] = (BM + wn * WN + r16) * BK_BYTES + pc;
+        const int pc = FP8 ? ((((2 * ks + (g >> 1)) ^ swz<BKB>(r16)) << 4) + 8 * (g & 1))
+                           : (((4 * ks + g) ^ swz<BKB>(r16)) << 4);
+        aoff[ks] = (wm * WM + r16) * BKB + pc;
+        woff[ks] = (BM + wn * WN + r16) * BKB + pc;
     }
 
     const int S = nn * nk;
@@ -174,17 +197,13 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
     for (int t = 0; t < nn; ++t) {
         for (int kt = 0; kt < nk; ++kt) {
             const int st = t * nk + kt;
-            // This wave's loads of stage st have landed once at most the LPW
-            // loads of stage st + 1 are outstanding; the barrier then makes
-            // all waves' parts of stage st visible and frees the stage read
-            // in iteration st - 1.  (A bare s_barrier: __syncthreads() would
-            // also drain the stage still in flight.)
-            if constexpr (AHEAD == 2) {
-                if (st + 1 < S) wait_vmcnt<LPW>();
-                else wait_vmcnt<0>();
-            } else {
-                wait_vmcnt<0>();
-            }
+            // This wave's loads of stage st have landed once at most the loads
+            // of the stages issued after it (up to AHEAD - 1 of them) are
+            // outstanding; the barrier then makes all waves' parts of stage st
+            // visible and frees the stage read in iteration st - 1.  (A bare
+            // s_barrier: __syncthreads() would also drain the stages still in
+            // flight.)
+            wait_stages<AHEAD - 1, LPW>(min(S - 1 - st, AHEAD - 1));
             __builtin_amdgcn_s_barrier();
             if (st + AHEAD < S) issue(st + AHEAD, (st + AHEAD) % STAGES);
             const unsigned char *sb = smem + (st % STAGES) * STAGE_BYTES;
@@ -193,9 +212,9 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
                 if constexpr (FP8) {
                     long af[TM], wf[TN];
 #pragma unroll
-                    for (int i = 0; i < TM; ++i) af[i] = *(const long *)(sb + aoff[ks] + 16 * i * BK_BYTES);
+                    for (int i = 0; i < TM; ++i) af[i] = *(const long *)(sb + aoff[ks] + 16 * i * BKB);
 #pragma unroll
-                    for (int j = 0; j < TN; ++j) wf[j] = *(const long *)(sb + woff[ks] + 16 * j * BK_BYTES);
+                    for (int j = 0; j < TN; ++j) wf[j] = *(const long *)(sb + woff[ks] + 16 * j * BKB);
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -204,9 +223,9 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
                 } else {
                     bf16x8 af[TM], wf[TN];
 #pragma unroll
-                    for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sb + aoff[ks] + 16 * i * BK_BYTES);
+                    for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sb + aoff[ks] + 16 * i * BKB);
 #pragma unroll
-                    for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sb + woff[ks] + 16 * j * BK_BYTES);
+                    for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sb + woff[ks] + 16 * j * BKB);
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -261,16 +280,18 @@ __global__ __launch_bounds__(NT, (BM == 128 ? 2 : 1)) void gemm_lds_kernel(const
 #endif
 }
 
-template <int BM, int BN, int STAGES, bool FP8>
+template <int BM, int BN, int BKB, int STAGES, int WGM, int WGN, int OCC, bool FP8>
 hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
-                      hipStream_t stream) {
-    constexpr size_t lds = (size_t)STAGES * (BM + BN) * BK_BYTES;
+                      hipStream_t stream, int tpw_default = 1) {
+    constexpr size_t lds = (size_t)STAGES * (BM + BN) * BKB;
+    static_assert(lds * OCC <= 160 * 1024, "LDS per CU");
+    constexpr int NTH = 64 * WGM * WGN;
     static bool attr_set = false;
     if (!attr_set) {
-        const void *fns[4] = {(const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_QKV, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_GELU, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_RESID, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, STAGES, EPI_STORE, FP8>};
+        const void *fns[4] = {(const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8>};
         for (const void *f : fns) {
             hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
@@ -283,16 +304,23 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
         const char *v = getenv("WM_GEMM_TPW");
         return v ? atoi(v) : 0;
     }();
-    const int tpw = tpw_env > 0 ? (tpw_env < ntn ? tpw_env : ntn) : 1;
+    const int tpw_req = tpw_env > 0 ? tpw_env : tpw_default;
+    const int tpw = tpw_req < ntn ? tpw_req : ntn;
     const int total = ((ntn + tpw - 1) / tpw) * ((M + BM - 1) / BM);
     const int grid = ((total + 7) >> 3) << 3;
-    const void *a = A;
-    const void *w = W;
     switch (epi) {
-    case EPI_QKV: gemm_lds_kernel<BM, BN, STAGES, EPI_QKV, FP8><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
-    case EPI_GELU: gemm_lds_kernel<BM, BN, STAGES, EPI_GELU, FP8><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
-    case EPI_RESID: gemm_lds_kernel<BM, BN, STAGES, EPI_RESID, FP8><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
-    default: gemm_lds_kernel<BM, BN, STAGES, EPI_STORE, FP8><<<grid, NT, lds, stream>>>(a, w, M, N, K, ep, tpw); break;
+    case EPI_QKV:
+        gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8><<<grid, NTH, lds, stream>>>(A, W, M, N, K, ep, tpw);
+        break;
+    case EPI_GELU:
+        gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8><<<grid, NTH, lds, stream>>>(A, W, M, N, K, ep, tpw);
+        break;
+    case EPI_RESID:
+        gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8><<<grid, NTH, lds, stream>>>(A, W, M, N, K, ep, tpw);
+        break;
+    default:
+        gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8><<<grid, NTH, lds, stream>>>(A, W, M, N, K, ep, tpw);
+        break;
     }
     return hipGetLastError();
 }
@@ -308,22 +336,39 @@ bool gemm_lds_applies(int M, int N, int K) {
 
 hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                            hipStream_t stream) {
-    // Default: 128x128 tiles, 2 stages (64 KB of LDS, two workgroups per CU,
-    // so one's epilogue overlaps the other's MFMA work).  WM_GEMM_CFG=2
-    // selects 256x128 tiles with 3 stages (one workgroup per CU), for tuning.
+    // Default for N a multiple of 256: 256x256 tiles, 8 waves (4 x 2, wave
+    // tile 64 x 128), 2 stages of 64 KB, one workgroup per CU; wide outputs
+    // (six or more feature tiles) walk two feature tiles per workgroup so the
+    // second tile's loads overlap the first one's epilogue.  Other N: 128x128
+    // tiles, 2 stages, two workgroups per CU.  WM_GEMM_CFG selects other
+    // shapes for tuning.
     static const int cfg = [] {
         const char *v = getenv("WM_GEMM_CFG");
-        return v ? atoi(v) : 0;
+        return v ? atoi(v) : -1;
     }();
-    if (cfg == 2) return launch_cfg<256, 128, 3, false>(A, W, M, N, K, epi, ep, stream);
-    return launch_cfg<128, 128, 2, false>(A, W, M, N, K, epi, ep, stream);
+    const bool n256 = N % 256 == 0;
+    switch (cfg) {
+    case 0: return launch_cfg<128, 128, 128, 2, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
+    case 3: return launch_cfg<256, 128, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
+    case 4: return launch_cfg<256, 128, 128, 3, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
+    case 9: return launch_cfg<256, 128, 64, 3, 4, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
+    default: break;
+    }
+    if (n256) return launch_cfg<256, 256, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, N >= 1536 ? 2 : 1);
+    return launch_cfg<128, 128, 128, 2, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
 }
 
 hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                            hipStream_t stream) {
     if (M <= 0) return hipSuccess;
     if (N % 128 || K % 128 || (unsigned long long)M * K >= (1ull << 32)) return hipErrorInvalidValue;
-    return launch_cfg<128, 128, 2, true>(A, W, M, N, K, epi, ep, stream);
+    static const int cfg = [] {
+        const char *v = getenv("WM_GEMM_CFG");
+        return v ? atoi(v) : -1;
+    }();
+    if (N % 256 == 0 && cfg != 0)
+        return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, N >= 1536 ? 2 : 1);
+    return launch_cfg<128, 128, 128, 2, 2, 2, 2, true>(A, W, M, N, K, epi, ep, stream);
 }
 
 }  // namespace wm
