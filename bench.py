@@ -27,6 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "latent processor-steps/s at 8x90x180 (BF16/FP8 vs FP32); p50/p99 serve latency"
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
+# v_exp_f32 at a quarter of the full VALU rate: 256 CUs x 4 SIMDs x 16 lanes / 4 x 2.4 GHz
+PEAK_EXP_GPS = 256 * 4 * 16 / 4 * 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_8x90x180.json")
 
 
@@ -48,6 +50,28 @@ def block_kernel_work(g, B=1, mlp=4):
         "mlp1": (2.0 * T * C * F, T * C * a + C * F * a + T * F * a),
         "mlp2": (2.0 * T * F * C, T * F * a + F * C * a + 2 * T * C * 4),
     }
+
+
+def roofline(g, kind, avg_us):
+    """Roofline of one block kernel: the resource whose peak gives the longest
+    minimum time for the kernel's algorithmic work (HBM bytes, MFMA FLOPs
+    and, for attention, exponentials) is the bound; frac = that minimum time
+    over the measured average."""
+    fl, by = block_kernel_work(g)[kind]
+    t = avg_us * 1e-6
+    cands = {"hbm": (by / (PEAK_HBM_GBS * 1e9), by / t / 1e9, PEAK_HBM_GBS, "GB/s")}
+    if kind not in ("ln1", "ln2"):
+        cands["mfma"] = (fl / (PEAK_BF16_TFLOPS * 1e12), fl / t / 1e12, PEAK_BF16_TFLOPS, "TFLOP/s")
+    if kind == "nat":
+        ne = g.T * g.heads * g.Kz * g.Ky * g.Kx
+        cands["exp"] = (ne / (PEAK_EXP_GPS * 1e9), ne / t / 1e9, PEAK_EXP_GPS, "Gexp/s")
+    bound = max(cands, key=lambda c: cands[c][0])
+    tmin, ach, peak, unit = cands[bound]
+    out = {"kernel": kind, "bound": bound, "achieved": round(ach, 2), "peak": peak, "unit": unit,
+           "frac": round(tmin / t, 4)}
+    out["others"] = {c: {"achieved": round(v[1], 2), "peak": v[2], "unit": v[3], "frac": round(v[0] / t, 4)}
+                     for c, v in cands.items() if c != bound}
+    return out
 
 
 def step_flops(g, nb=8, B=1, mlp=4):
@@ -299,18 +323,15 @@ def main():
                              "tflops": round(fl / (avg * 1e-3) / 1e12, 2),
                              "gbs": round(by / (avg * 1e-3) / 1e9, 1)}
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"])
-    d = per_kernel[dom]
-    if dom in ("ln1", "ln2"):
-        roof = {"kernel": dom, "bound": "hbm", "achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(d["gbs"] / PEAK_HBM_GBS, 4)}
-    else:
-        roof = {"kernel": dom, "bound": "mfma", "achieved": d["tflops"], "peak": PEAK_BF16_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(d["tflops"] / PEAK_BF16_TFLOPS, 4)}
+    roof = roofline(g, dom, per_kernel[dom]["avg_us"])
     roof["traffic"] = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
         if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("kernels", {}):
             roof["traffic"] = tr["kernels"][dom]["hbm_bytes_per_launch"]
+    for k in per_kernel:
+        r = roofline(g, k, per_kernel[k]["avg_us"])
+        per_kernel[k]["bound"], per_kernel[k]["frac"] = r["bound"], r["frac"]
     flops = step_flops(g, nb)
     out = {
         "metric": METRIC, "value": round(sps, 3), "unit": "processor-steps/s",

@@ -43,6 +43,8 @@ constexpr int XW = 16;                    // halo lon extent, padded (>= TX + Kx
 constexpr int XT = 9;                     // bias table lon extent: hx - xq_rel + 1
 constexpr float TAU = 8.0f;               // lazy rescale threshold (log2 units)
 constexpr int LD_BATCH = 4;               // halo items loaded before they are stored
+constexpr int NEG_RUN = 64;               // -inf entries after the bias table (>= 6 XT + 4)
+constexpr int YR_MIN = 10;                // lat rows per level slab a chunk walk may read (2 + 8)
 
 __device__ __forceinline__ void clamp_range(int a0, int tsize, int N, int K, int &lo, int &n) {
     const int last = min(a0 + tsize - 1, N - 1);
@@ -70,11 +72,12 @@ __device__ __forceinline__ float xmax16_32(float v) {
 // it into the QKV projection); otherwise scores are scaled after the MFMA and
 // the bias table is stored divided by that scale.
 template <int KZ, int KY, int KX>
-constexpr int tbl_padded() { return ((2 * KZ - 1) * (2 * KY - 1) * XT + 4 + 3) & ~3; }
+constexpr int tbl_padded() { return ((2 * KZ - 1) * (2 * KY - 1) * XT + NEG_RUN + 3) & ~3; }
 
 // Per-head bias table in the layout the tile kernel reads: tbl[iz][iy][ixt]
 // (ixt = key lon slot - query lon slot + 1), lon validity folded in as
-// -inf, followed by 4 entries of -inf that masked (level, lat) rows read.
+// -inf, followed by a run of NEG_RUN entries of -inf that masked (level,
+// lat) rows read.
 template <int KZ, int KY, int KX, bool QSCALED>
 __global__ void nat_bias_prep(NatArgs p) {
     constexpr int RX = (KX - 1) / 2, BY = 2 * KY - 1, BZ = 2 * KZ - 1;
@@ -93,19 +96,16 @@ __global__ void nat_bias_prep(NatArgs p) {
 }
 
 template <int KZ, int KY, int KX, bool QSCALED>
-__global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, int YWmax) {
+__global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, int YR) {
     constexpr int RX = (KX - 1) / 2;
     constexpr int BY = 2 * KY - 1;
-    constexpr int BZ = 2 * KZ - 1;
-    constexpr int NCH = 2 * (4 + KZ - 1);           // max chunks per group
-    constexpr int TBL = BZ * BY * XT;               // bias table entries
+    constexpr int TBL = (2 * KZ - 1) * BY * XT;    // bias table entries
     static_assert(2 + KX - 1 <= 8 && 2 + KY - 1 <= 8, "window too large for the 8-wide group halo");
-    static_assert(NCH <= 16, "chunk mask is 32 bits");
 
     constexpr int TBLP = tbl_padded<KZ, KY, KX>();
     extern __shared__ __align__(16) unsigned char smem[];
-    float *tbl = (float *)smem;                                  // [BZ][BY][XT] + 4 x -inf
-    const int nslot_max = ZWmax * YWmax * XW;
+    float *tbl = (float *)smem;                                  // [BZ][BY][XT] + a run of -inf
+    const int nslot_max = ZWmax * YR * XW;
     const int VS = nslot_max + 4;                                // Vt row stride (elements)
     unsigned char *Vtb = smem + TBLP * 4;                        // [32][VS] bf16
 
@@ -129,7 +129,6 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
     clamp_range(z0, TZ, p.Z, KZ, zlo, zn);
     clamp_range(y0, TY, p.Y, KY, ylo, yn);
     const int xlo = x0 - RX;                       // periodic lon
-    const int nslot = zn * yn * XW;
 
     const bf16 *kb = (const bf16 *)p.k + (size_t)b * p.bs + (size_t)h * p.hs;
     const bf16 *vb = (const bf16 *)p.v + (size_t)b * p.bs + (size_t)h * p.hs;
@@ -141,12 +140,15 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         const uint4 *src = (const uint4 *)(p.tbl_ws + (size_t)h * TBLP);
         for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
     }
-    // ---- V halo, transposed.  Item = (slot pair, 16-byte chunk c), c
-    // fastest: 4 lanes read the 2 x 64 contiguous bytes of two neighbouring
-    // tokens.  Loads of a batch are issued before any store (items past the
-    // end reload the last item and are not stored).
+    // ---- V halo, transposed: slot (hz, hy, hx) at (hz YR + hy) XW + hx.
+    // Item = (slot pair, 16-byte chunk c), c fastest: 4 lanes read the 2 x 64
+    // contiguous bytes of two neighbouring tokens.  Loads of a batch are
+    // issued before any store (items past the end reload the last item and
+    // are not stored).  Rows yn .. YR-1 of each level are zeroed: the chunk
+    // walk reads them for keys outside every window (weight 0), and 0 x V
+    // must stay 0.
     {
-        const int nitems = nslot * 2;
+        const int nitems = zn * yn * XW * 2;
         unsigned *Vt32 = (unsigned *)Vtb;
         for (int e0 = tid; e0 < nitems; e0 += 256 * LD_BATCH) {
             uint4 v0[LD_BATCH], v1[LD_BATCH];
@@ -170,7 +172,9 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
                 const int e = e0 + 256 * u;
                 if (e < nitems) {
                     const int pr = e >> 2, c = e & 3;
-                    unsigned *vrow = Vt32 + (8 * c) * (VS >> 1) + pr;
+                    const int row = (2 * pr) / XW;
+                    const int prs = pr + (row / yn) * (YR - yn) * (XW / 2);   // pair index in the YR layout
+                    unsigned *vrow = Vt32 + (8 * c) * (VS >> 1) + prs;
                     vrow[0 * (VS >> 1)] = (v0[u].x & 0xffffu) | (v1[u].x << 16);
                     vrow[1 * (VS >> 1)] = (v0[u].x >> 16) | (v1[u].x & 0xffff0000u);
                     vrow[2 * (VS >> 1)] = (v0[u].y & 0xffffu) | (v1[u].y << 16);
@@ -180,6 +184,15 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
                     vrow[6 * (VS >> 1)] = (v0[u].w & 0xffffu) | (v1[u].w << 16);
                     vrow[7 * (VS >> 1)] = (v0[u].w >> 16) | (v1[u].w & 0xffff0000u);
                 }
+            }
+        }
+        if (yn < YR) {
+            const int gap = (YR - yn) * (XW / 2);              // dword columns per level
+            const int nz = zn * gap * 32;
+            for (int e = tid; e < nz; e += 256) {
+                const int d = e & 31, col = e >> 5;
+                const int hz = col / gap, cg = col - hz * gap;
+                Vt32[d * (VS >> 1) + (hz * YR + yn) * (XW / 2) + cg] = 0u;
             }
         }
     }
@@ -196,47 +209,47 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
 
     int ylg, yng;
     clamp_range(min(y0g, p.Y - 1), 2, p.Y, KY, ylg, yng);
-    const int nch = 2 * zn;                      // the group spans the tile's 4 levels
     const int dy = ylg - ylo;
     const int wz = win_start(zc, p.Z, KZ, false) - zlo;
     const int wy = win_start(yc, p.Y, KY, false) - ylg;
     const int zb = zlo - zc + KZ - 1;
     const int yb = ylg - yc + KY - 1;
 
-    // validity of (level row, lat row) for this lane's query: bit 2c + j
-    unsigned vmask = 0;
+    // Validity of this lane's key rows for its query: lat row part (chunk
+    // half hf, MFMA block j) is loop-invariant; the level part is tested
+    // per level.  Both are lane masks, so combining them is scalar work.
+    bool oky[2][2];
 #pragma unroll
-    for (int c = 0; c < NCH; ++c)
+    for (int hf = 0; hf < 2; ++hf)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int hz = c >> 1, hy = 4 * (c & 1) + 2 * j + (g >> 1);
-            const bool ok = c < nch && (unsigned)(hz - wz) < (unsigned)KZ && (unsigned)(hy - wy) < (unsigned)KY;
-            vmask |= (ok ? 1u : 0u) << (2 * c + j);
-        }
+        for (int j = 0; j < 2; ++j)
+            oky[hf][j] = (unsigned)(4 * hf + 2 * j + (g >> 1) - wy) < (unsigned)KY;
+    // bias table index of this lane's first key at level 0 of the halo
     const int tb_lane = (zb * BY + yb + (g >> 1)) * XT + 4 * (g & 1) - xrel + 1;
 
-    // Lane-constant byte offsets of the K operand (key 16j + r16 of a chunk;
-    // global memory, within level zlo) and of the V^T operand (keys
-    // 16j + 4g + i; LDS, within level slab 0), for q = 2 * (c & 1) + j and
-    // the wave's two groups G.
+    // K operand: key 16j + r16 of a chunk = lat row 4hf + 2j + (r16 >> 3),
+    // lon column r16 & 7 of the group halo, read from global memory (byte
+    // offsets within level zlo; the level advances through the scalar offset).
     const __amdgpu_buffer_rsrc_t krs = __builtin_amdgcn_make_buffer_rsrc(
         uniform_ptr(kb), 0, 0x7ffffffe, 0x00020000);
     const int tsb = (int)p.ts * 2;                          // token stride, bytes
-    int kofs[4][2], vofs[4][2];
+    int kofs[4][2];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int hyk = min(4 * (q >> 1) + 2 * (q & 1) + (r16 >> 3) + dy, yn - 1);
-        const int hyv = min(4 * (q >> 1) + 2 * (q & 1) + (g >> 1) + dy, yn - 1);
 #pragma unroll
         for (int G = 0; G < 2; ++G) {
-            const int xg = GX * (gxa + G);
-            int xk = xlo + (r16 & 7) + xg;
+            int xk = xlo + (r16 & 7) + GX * (gxa + G);
             xk = xk < 0 ? xk + p.X : (xk >= p.X ? xk - p.X : xk);
             kofs[q][G] = (((zlo * p.Y) + ylo + hyk) * p.X + xk) * tsb + 16 * g;
-            vofs[q][G] = (r16 * VS + hyv * XW + 4 * (g & 1) + xg) * 2;
         }
     }
-    const int kslab = p.Y * p.X * tsb, vslab = yn * XW * 2;
+    const int kslab = p.Y * p.X * tsb;
+    // V^T operand (keys 16j + 4g + i): lane base at level 0 for the two
+    // 16-channel halves tt; lat row, group and key offsets are immediates.
+    const int vbase0 = (r16 * VS + ((g >> 1) + dy) * XW + 4 * (g & 1) + GX * gxa) * 2;
+    const int vbase1 = vbase0 + 16 * VS * 2;
+    const int vslab = YR * XW * 2;
 
     // Q fragments of the two groups
     bf16x8 qf[2];
@@ -262,8 +275,8 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
 #pragma unroll
     for (int e = 0; e < 8; ++e) ones[e] = __builtin_bit_cast(bf16, (unsigned short)0x3f80);
 
-    // K fragments ping-pong between two register sets: chunk c uses
-    // kreg[c & 1] while chunk c + 1 is in flight into the other.
+    // K fragments ping-pong between two register sets: half hf of a level
+    // uses kreg[hf] while the next chunk is in flight into the other set.
     bf16x8 kreg[2][2][2];
 #pragma unroll
     for (int G = 0; G < 2; ++G)
@@ -271,28 +284,33 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         for (int j = 0; j < 2; ++j)
             kreg[0][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(krs, kofs[j][G], 0, 0));
 
+    for (int hz = 0; hz < zn; ++hz) {
+        const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
+        const unsigned char *vz0 = Vtb + vbase0 + hz * vslab;
+        const unsigned char *vz1 = Vtb + vbase1 + hz * vslab;
+        const int tbh = tb_lane + hz * BY * XT;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        if (c < nch) {
-            const int hz = c >> 1;
-            const unsigned char *Vz = Vtb + hz * vslab;
-            if (c + 1 < nch) {
-                const int cn = c + 1;
+        for (int hf = 0; hf < 2; ++hf) {
+            {   // next chunk: (hz, 1) or (hz + 1, 0); the last level reloads itself
+                const int nh = hf ^ 1;
+                // uniform; readfirstlane lets the scalar offset take it directly
+                const int soff = __builtin_amdgcn_readfirstlane((hf ? min(hz + 1, zn - 1) : hz) * kslab);
 #pragma unroll
                 for (int G = 0; G < 2; ++G)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        kreg[cn & 1][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
-                            krs, kofs[2 * (cn & 1) + j][G], (cn >> 1) * kslab, 0));
+                        kreg[nh][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
+                            krs, kofs[2 * nh + j][G], soff, 0));
             }
-            // bias + mask tile (shared by both groups)
+            // bias + mask tile (shared by both groups); masked rows read
+            // the run of -inf past the table
             f32x4 binit[2];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const bool ok = (vmask >> (2 * c + j)) & 1u;
-                const int a = ok ? tb_lane + hz * BY * XT + (4 * (c & 1) + 2 * j) * XT : TBL;
+                const int a = (okz && oky[hf][j]) ? tbh : TBL;
+                const float *tp = tbl + a + (4 * hf + 2 * j) * XT;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) binit[j][i] = tbl[a + i];
+                for (int i = 0; i < 4; ++i) binit[j][i] = tp[i];
             }
             // scores of both groups
             f32x4 s[2][2];
@@ -301,23 +319,23 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
             for (int G = 0; G < 2; ++G)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    s[G][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kreg[c & 1][G][j], qf[G], binit[j], 0, 0, 0);
+                    s[G][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kreg[hf][G][j], qf[G], binit[j], 0, 0, 0);
                     if constexpr (!QSCALED) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) s[G][j][i] *= p.qscale;
                     }
                 }
 #pragma unroll
-            for (int G = 0; G < 2; ++G) {
+            for (int G = 0; G < 2; ++G)
                 cm[G] = fmaxf(fmaxf(fmaxf(s[G][0][0], s[G][0][1]), fmaxf(s[G][0][2], s[G][0][3])),
                               fmaxf(fmaxf(s[G][1][0], s[G][1][1]), fmaxf(s[G][1][2], s[G][1][3])));
-                cm[G] = xmax16_32(cm[G]);
-            }
-            // move the reference maxima only when a chunk exceeds them by TAU
+            // Move the reference maxima only when some lane's scores exceed
+            // them by TAU; the new maximum is taken over the 4 lanes that
+            // share each query, so all of them keep the same reference.
             if (__builtin_amdgcn_ballot_w64(cm[0] > mref[0] + TAU || cm[1] > mref[1] + TAU)) {
 #pragma unroll
                 for (int G = 0; G < 2; ++G) {
-                    const float mn = fmaxf(mref[G], cm[G]);
+                    const float mn = fmaxf(mref[G], xmax16_32(cm[G]));
                     const float al = __builtin_amdgcn_exp2f(mref[G] - mn);
                     mref[G] = mn;
 #pragma unroll
@@ -340,18 +358,14 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
             for (int G = 0; G < 2; ++G) {
 #pragma unroll
                 for (int tt = 0; tt < 2; ++tt) {
-                    bf16x8 vf;
-#pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const unsigned char *vp = Vz + vofs[2 * (c & 1) + j][G] + tt * 16 * VS * 2;
-                        const unsigned w0 = *(const unsigned *)vp;
-                        const unsigned w1 = *(const unsigned *)(vp + 4);
-                        vf[4 * j + 0] = __builtin_bit_cast(bf16, (unsigned short)(w0 & 0xffffu));
-                        vf[4 * j + 1] = __builtin_bit_cast(bf16, (unsigned short)(w0 >> 16));
-                        vf[4 * j + 2] = __builtin_bit_cast(bf16, (unsigned short)(w1 & 0xffffu));
-                        vf[4 * j + 3] = __builtin_bit_cast(bf16, (unsigned short)(w1 >> 16));
-                    }
-                    oacc[G][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(vf, pb[G], oacc[G][tt], 0, 0, 0);
+                    const unsigned char *vz = tt ? vz1 : vz0;
+                    uint4 w;
+                    w.x = *(const unsigned *)(vz + (4 * hf) * XW * 2 + 4 * G);
+                    w.y = *(const unsigned *)(vz + (4 * hf) * XW * 2 + 4 * G + 4);
+                    w.z = *(const unsigned *)(vz + (4 * hf + 2) * XW * 2 + 4 * G);
+                    w.w = *(const unsigned *)(vz + (4 * hf + 2) * XW * 2 + 4 * G + 4);
+                    oacc[G][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w), pb[G],
+                                                                          oacc[G][tt], 0, 0, 0);
                 }
                 lacc[G] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, pb[G], lacc[G], 0, 0, 0);
             }
@@ -385,16 +399,16 @@ int max_halo(int N, int K, int tsize) {
     return m;
 }
 
-size_t tile_lds(int Kz, int Ky, int zw, int yw) {
-    const int tblp = (((2 * Kz - 1) * (2 * Ky - 1) * XT + 4 + 3) & ~3);
-    const size_t nslot = (size_t)zw * yw * XW;
+size_t tile_lds(int Kz, int Ky, int zw, int yr) {
+    const int tblp = (((2 * Kz - 1) * (2 * Ky - 1) * XT + NEG_RUN + 3) & ~3);
+    const size_t nslot = (size_t)zw * yr * XW;
     return (size_t)tblp * 4 + 32 * (nslot + 4) * 2;
 }
 
 template <int KZ, int KY, int KX, bool QSCALED>
 hipError_t launch_tile_q(const NatArgs &a, hipStream_t stream) {
-    const int zw = max_halo(a.Z, KZ, TZ), yw = max_halo(a.Y, KY, TY);
-    const size_t lds = tile_lds(KZ, KY, zw, yw);
+    const int zw = max_halo(a.Z, KZ, TZ), yr = std::max(max_halo(a.Y, KY, TY), YR_MIN);
+    const size_t lds = tile_lds(KZ, KY, zw, yr);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void *)nat_tile_kernel<KZ, KY, KX, QSCALED>,
@@ -407,7 +421,7 @@ hipError_t launch_tile_q(const NatArgs &a, hipStream_t stream) {
     const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
     const long total = (long)ntiles * a.H * a.B;
     const unsigned grid = (unsigned)(((total + 7) >> 3) << 3);
-    nat_tile_kernel<KZ, KY, KX, QSCALED><<<grid, 256, lds, stream>>>(a, zw, yw);
+    nat_tile_kernel<KZ, KY, KX, QSCALED><<<grid, 256, lds, stream>>>(a, zw, yr);
     return hipGetLastError();
 }
 
@@ -428,7 +442,7 @@ size_t nat_tile_lds_bytes(const NatArgs &a) {
     if (!a.tbl_ws) return 0;
     // K is addressed with 32-bit byte offsets from the state's base
     if ((long)a.Z * a.Y * a.X * a.ts * 2 >= (1L << 31)) return 0;
-    return tile_lds(a.Kz, a.Ky, max_halo(a.Z, a.Kz, TZ), max_halo(a.Y, a.Ky, TY));
+    return tile_lds(a.Kz, a.Ky, max_halo(a.Z, a.Kz, TZ), std::max(max_halo(a.Y, a.Ky, TY), YR_MIN));
 }
 
 hipError_t launch_nat_tile(const NatArgs &a, hipStream_t stream) {
