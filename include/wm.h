@@ -107,9 +107,15 @@ int wm_nat_indices(const wm_grid *g, int *dev_out, void *stream);
  *   out_h(n) = sum over m in the window of n of softmax_m(s) v_h(m)
  * with (dz,dy,dx) = key - query offsets (periodic axes: t - r).
  * q, k, v, out: device [B][Z*Y*X][heads][d] in float32 (WM_F32) or
- * bfloat16 (WM_BF16); rpb: device float32 [heads][2Kz-1][2Ky-1][2Kx-1].
- * Softmax max and sum are float32.  WM_FP8_E4M3 is rejected here (FP8 is
- * a processor precision).  Uses the context workspace. */
+ * bfloat16 (WM_BF16 and WM_FP8_E4M3); rpb: device float32
+ * [heads][2Kz-1][2Ky-1][2Kx-1].  Softmax max and sum are float32.
+ * WM_FP8_E4M3 runs both contractions on OCP e4m3 codes: q, k and v of each
+ * state are quantized with the scale amax/448 of that state's tensor (round
+ * to nearest even, saturating), the softmax weights with the static scale 1
+ * (they are <= 256 by construction), and the output is dequantized to bf16;
+ * it needs a lon-periodic grid (periodic_mask 4), a 5x7x7, 3x5x5 or 3x3x3
+ * window, X >= Kx + 7 and B <= 64 (else WM_EINVAL).  Uses the context
+ * workspace. */
 int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec,
                    const void *q, const void *k, const void *v,
                    const float *rpb, void *out, void *stream);

@@ -163,11 +163,14 @@ int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec, cons
     if (rc) return rc;
     if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
     if (B < 0) return fail(WM_EINVAL, "negative batch");
-    if (prec != WM_F32 && prec != WM_BF16) return fail(WM_EINVAL, "wm_nat_forward takes WM_F32 or WM_BF16");
+    if (prec != WM_F32 && prec != WM_BF16 && prec != WM_FP8_E4M3) return fail(WM_EINVAL, "unknown precision");
     if (B == 0) return WM_OK;
     if (!q || !k || !v || !rpb || !out) return fail(WM_EINVAL, "NULL tensor");
     const long T = (long)g->Z * g->Y * g->X;
-    rc = ctx_reserve(ctx, (size_t)g->heads * NAT_TBL_WS_FLOATS * 4);
+    const bool fp8 = prec == WM_FP8_E4M3;
+    if (fp8 && B > 64) return fail(WM_EINVAL, "FP8 attention takes at most 64 states per call");
+    const size_t tbl_bytes = (size_t)(fp8 ? B : 1) * g->heads * NAT_TBL_WS_FLOATS * 4;
+    rc = ctx_reserve(ctx, tbl_bytes + (fp8 ? (size_t)AMAX_SHARDS * AMAX_STRIDE * 4 : 0));
     if (rc) return rc;
     NatArgs a{};
     a.q = q; a.k = k; a.v = v;
@@ -179,7 +182,23 @@ int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec, cons
     a.B = B; a.Z = g->Z; a.Y = g->Y; a.X = g->X; a.H = g->heads;
     a.Kz = g->Kz; a.Ky = g->Ky; a.Kx = g->Kx; a.periodic = g->periodic_mask;
     a.tbl_ws = (float *)ctx->ws;
-    hipError_t e = launch_nat(a, prec == WM_BF16, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (fp8) {
+        if (nat_tile_lds_bytes(a) == 0)   // a.amax is still null: asks whether the tiled kernels apply
+            return fail(WM_EINVAL, "FP8 attention needs lon-periodic only, a 5x7x7, 3x5x5 or 3x3x3 window "
+                                   "and lon >= 8 + Kx - 1");
+        unsigned *amax = (unsigned *)((char *)ctx->ws + tbl_bytes);
+        if ((e = launch_zero_u32(amax, (size_t)AMAX_SHARDS * AMAX_STRIDE, s)) != hipSuccess) return hip_fail(e, "zero");
+        const void *src[3] = {q, k, v};
+        for (int i = 0; i < 3; ++i)
+            if ((e = launch_amax_bf16(src[i], (size_t)T * g->C, B, amax + i, 3, s)) != hipSuccess)
+                return hip_fail(e, "amax");
+        if ((e = launch_amax_fold(amax, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
+        a.amax = (const float *)amax;
+        a.amax_stride = 3;
+    }
+    e = launch_nat(a, prec != WM_F32, s);
     return e == hipSuccess ? WM_OK : hip_fail(e, "nat launch");
 }
 
@@ -435,8 +454,8 @@ double wm_relerr_l2(wm_ctx *ctx, const float *y, const double *y_ref, size_t n, 
     if (!ctx || !y || !y_ref) return (double)fail(WM_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
-    if ((e = hipMemsetAsync(ctx->small, 0, 2 * sizeof(double), s)) != hipSuccess)
-        return (double)hip_fail(e, "memset");
+    if ((e = launch_zero_u32((unsigned *)ctx->small, 4, s)) != hipSuccess)
+        return (double)hip_fail(e, "zero");
     if ((e = launch_relerr(y, y_ref, n, (double *)ctx->small, s)) != hipSuccess) return (double)hip_fail(e, "relerr");
     double h[2];
     if ((e = hipMemcpyAsync(h, ctx->small, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess)

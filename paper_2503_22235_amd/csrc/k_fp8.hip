@@ -142,6 +142,31 @@ __global__ __launch_bounds__(256) void quant_f32_kernel(const float *__restrict_
     }
 }
 
+// amax over each state's bf16 elements (8 per lane per step).
+__global__ __launch_bounds__(256) void amax_bf16_kernel(const unsigned short *__restrict__ x, size_t per_state,
+                                                        unsigned *__restrict__ amax, int amax_stride) {
+    const int b = blockIdx.y;
+    const unsigned short *xs = x + (size_t)b * per_state;
+    float m = 0.f;
+    const size_t n8 = per_state / 8;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n8; i += (size_t)gridDim.x * 256) {
+        const uint4 u = *(const uint4 *)(xs + 8 * i);
+        const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            m = fmaxf(m, fmaxf(fabsf(__uint_as_float(w[q] << 16)), fabsf(__uint_as_float(w[q] & 0xffff0000u))));
+    }
+    for (size_t i = n8 * 8 + (size_t)blockIdx.x * 256 + threadIdx.x; i < per_state; i += (size_t)gridDim.x * 256)
+        m = fmaxf(m, fabsf(__uint_as_float((unsigned)xs[i] << 16)));
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0)
+        atomicMax(amax + (blockIdx.x % AMAX_SHARDS) * AMAX_STRIDE + b * amax_stride, __float_as_uint(m));
+}
+
+__global__ void zero_u32_kernel(unsigned *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = 0u;
+}
+
 template <int VPT>
 hipError_t ln_fp8(const float *x, const float *g, const float *b, int M, int T, float eps, unsigned *amax,
                   unsigned char *out, hipStream_t s) {
@@ -172,6 +197,25 @@ hipError_t launch_quant_rows(const void *in_bf16, int M, int F, int T, const flo
     if (M <= 0) return hipSuccess;
     if (F % 8) return hipErrorInvalidValue;
     quant_rows_kernel<<<(M + 3) / 4, 256, 0, stream>>>((const bf16 *)in_bf16, M, F, T, amax, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_amax_bf16(const void *x, size_t per_state, int B, unsigned *amax, int amax_stride,
+                            hipStream_t stream) {
+    if (B <= 0 || per_state == 0) return hipSuccess;
+    size_t bx = (per_state / 8 + 255) / 256;
+    if (bx > 1024) bx = 1024;
+    if (bx == 0) bx = 1;
+    amax_bf16_kernel<<<dim3((unsigned)bx, (unsigned)B), 256, 0, stream>>>((const unsigned short *)x, per_state, amax,
+                                                                         amax_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned *p, size_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    zero_u32_kernel<<<(unsigned)blocks, 256, 0, stream>>>(p, n);
     return hipGetLastError();
 }
 

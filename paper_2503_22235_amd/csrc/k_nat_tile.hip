@@ -388,6 +388,353 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP8 variant: both contractions run on e4m3 codes (gfx950 MFMA
+// 16x16x32 fp8, 8-byte fragments in the bf16 layout).  Q, K and V arrive
+// in bf16 with per-(state, tensor) amax values and are quantized with the
+// state's scale amax/448 as they are staged: K and V halos go to LDS as
+// e4m3 (K token-major with 32 bytes per token, V transposed), Q stays in
+// registers.  A score leaves the MFMA in units of c = s_q s_k qscale; the
+// bias table (per state and head) is stored divided by c, the reference
+// maximum is kept in those raw units, and the weights are
+// p = exp2(c (s - m)) <= 2^TAU, quantized with the static scale 1.
+// O = (sum_k p_k v_k) s_v / (sum_k p_k), both sums from the same e4m3 p.
+
+__device__ __forceinline__ float dq_scale(float amax) { return amax > 0.f ? amax * (1.0f / 448.0f) : 1.0f; }
+__device__ __forceinline__ float q_mul(float amax) { return amax > 0.f ? 448.0f / amax : 1.0f; }
+__device__ __forceinline__ float clamp448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
+
+// 8 bf16 values -> 8 e4m3 codes of value * mul (round to nearest even,
+// saturated); byte i of the result is value i.
+__device__ __forceinline__ uint2 bf16x8_to_e4m3(uint4 u, float mul) {
+    const unsigned w[4] = {u.x, u.y, u.z, u.w};
+    float f[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        f[2 * q] = __uint_as_float(w[q] << 16) * mul;
+        f[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u) * mul;
+    }
+    uint2 o;
+    unsigned a = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(f[0]), clamp448(f[1]), 0, false);
+    o.x = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(f[2]), clamp448(f[3]), (int)a, true);
+    a = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(f[4]), clamp448(f[5]), 0, false);
+    o.y = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(f[6]), clamp448(f[7]), (int)a, true);
+    return o;
+}
+
+constexpr int KRS = XW * 32 + 16;   // K halo bytes per lat row (16-byte pad against bank conflicts)
+
+// V^T row stride in bytes: >= the halo slots, = 8 mod 128.
+__host__ __device__ inline int vt_row_bytes(int zw, int yr) { return (zw * yr * XW + 119) / 128 * 128 + 8; }
+
+// Per-(state, head) bias table divided by that state's score unit c.
+template <int KZ, int KY, int KX>
+__global__ void nat_bias_prep_fp8(NatArgs p) {
+    constexpr int RX = (KX - 1) / 2, BY = 2 * KY - 1, BZ = 2 * KZ - 1;
+    constexpr int TBL = BZ * BY * XT, TBLP = tbl_padded<KZ, KY, KX>();
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= p.B * p.H * TBLP) return;
+    const int bh = e / TBLP, i = e - bh * TBLP;
+    const int b = bh / p.H, h = bh - b * p.H;
+    const float c = dq_scale(p.amax[(size_t)b * p.amax_stride]) * dq_scale(p.amax[(size_t)b * p.amax_stride + 1]) *
+                    p.qscale;
+    float v = -INFINITY;
+    if (i < TBL) {
+        const int ixt = i % XT, rest = i / XT;
+        const int dx = ixt - 1 - RX;
+        if (dx >= -RX && dx <= RX) v = p.rpb[((size_t)h * BZ * BY + rest) * (2 * KX - 1) + dx + KX - 1] * p.bscale / c;
+    }
+    p.tbl_ws[e] = v;
+}
+
+template <int KZ, int KY, int KX>
+__global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWmax, int YR) {
+    constexpr int RX = (KX - 1) / 2;
+    constexpr int BY = 2 * KY - 1;
+    constexpr int TBL = (2 * KZ - 1) * BY * XT;
+    static_assert(2 + KX - 1 <= 8 && 2 + KY - 1 <= 8, "window too large for the 8-wide group halo");
+    constexpr int TBLP = tbl_padded<KZ, KY, KX>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *tbl = (float *)smem;
+    unsigned char *Ks = smem + TBLP * 4;                     // [ZWmax*YR lat rows][KRS]
+    const int VSB = vt_row_bytes(ZWmax, YR);
+    unsigned char *Vt = Ks + (size_t)ZWmax * YR * KRS;       // [32][VSB]
+
+    const int ntz = (p.Z + TZ - 1) / TZ, nty = (p.Y + TY - 1) / TY, ntx = (p.X + TX - 1) / TX;
+    const int ntiles = ntz * nty * ntx;
+    const int total = ntiles * p.H * p.B;
+    const int per = (total + 7) >> 3;
+    const int L = blockIdx.x;
+    const int id = (L & 7) * per + (L >> 3);
+    if (id >= total) return;
+    int t = id;
+    const int tx = t % ntx; t /= ntx;
+    const int ty = t % nty; t /= nty;
+    const int tz = t % ntz; t /= ntz;
+    const int h = t % p.H;
+    const int b = t / p.H;
+    const int z0 = tz * TZ, y0 = ty * TY, x0 = tx * TX;
+
+    int zlo, zn, ylo, yn;
+    clamp_range(z0, TZ, p.Z, KZ, zlo, zn);
+    clamp_range(y0, TY, p.Y, KY, ylo, yn);
+    const int xlo = x0 - RX;
+
+    const bf16 *kb = (const bf16 *)p.k + (size_t)b * p.bs + (size_t)h * p.hs;
+    const bf16 *vb = (const bf16 *)p.v + (size_t)b * p.bs + (size_t)h * p.hs;
+    const bf16 *qb = (const bf16 *)p.q + (size_t)b * p.bs + (size_t)h * p.hs;
+    const float aq = p.amax[(size_t)b * p.amax_stride], ak = p.amax[(size_t)b * p.amax_stride + 1],
+                av = p.amax[(size_t)b * p.amax_stride + 2];
+    const float c = dq_scale(aq) * dq_scale(ak) * p.qscale;     // score unit, log2 domain
+    const float mulk = q_mul(ak), mulv = q_mul(av);
+    const int tid = threadIdx.x;
+
+    {
+        const uint4 *src = (const uint4 *)(p.tbl_ws + ((size_t)b * p.H + h) * TBLP);
+        for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
+    }
+    // ---- K halo, token-major e4m3: item = (slot, 16-byte chunk c of 8 channels)
+    {
+        const int nitems = zn * yn * XW * 4;
+        for (int e0 = tid; e0 < nitems; e0 += 256 * LD_BATCH) {
+            uint4 raw[LD_BATCH];
+#pragma unroll
+            for (int u = 0; u < LD_BATCH; ++u) {
+                const int e = min(e0 + 256 * u, nitems - 1);
+                const int slot = e >> 2, cc = e & 3;
+                const int hx = slot % XW, row = slot / XW;
+                const int hy = row % yn, hz = row / yn;
+                int xc = xlo + (hx < TX + KX - 1 ? hx : 0);
+                xc = xc < 0 ? xc + p.X : (xc >= p.X ? xc - p.X : xc);
+                const long rtok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X;
+                raw[u] = *(const uint4 *)(kb + (size_t)(rtok + xc) * p.ts + 8 * cc);
+            }
+#pragma unroll
+            for (int u = 0; u < LD_BATCH; ++u) {
+                const int e = e0 + 256 * u;
+                if (e < nitems) {
+                    const int slot = e >> 2, cc = e & 3;
+                    const int hx = slot % XW, row = slot / XW;
+                    const int hy = row % yn, hz = row / yn;
+                    *(uint2 *)(Ks + (hz * YR + hy) * KRS + hx * 32 + 8 * cc) = bf16x8_to_e4m3(raw[u], mulk);
+                }
+            }
+        }
+    }
+    // ---- V halo, transposed e4m3: item = (4 neighbouring slots, chunk c)
+    {
+        const int nitems = zn * yn * (XW / 4) * 4;
+        for (int e0 = tid; e0 < nitems; e0 += 256 * (LD_BATCH / 2)) {
+            uint4 raw[LD_BATCH / 2][4];
+#pragma unroll
+            for (int u = 0; u < LD_BATCH / 2; ++u) {
+                const int e = min(e0 + 256 * u, nitems - 1);
+                const int qd = e >> 2, cc = e & 3;
+                const int slot = 4 * qd;
+                const int hx = slot % XW, row = slot / XW;
+                const int hy = row % yn, hz = row / yn;
+                const long rtok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X;
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    int xc = xlo + (hx + w < TX + KX - 1 ? hx + w : 0);
+                    xc = xc < 0 ? xc + p.X : (xc >= p.X ? xc - p.X : xc);
+                    raw[u][w] = *(const uint4 *)(vb + (size_t)(rtok + xc) * p.ts + 8 * cc);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < LD_BATCH / 2; ++u) {
+                const int e = e0 + 256 * u;
+                if (e < nitems) {
+                    const int qd = e >> 2, cc = e & 3;
+                    const int slot = 4 * qd;
+                    const int hx = slot % XW, row = slot / XW;
+                    const int hy = row % yn, hz = row / yn;
+                    uint2 cv[4];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) cv[w] = bf16x8_to_e4m3(raw[u][w], mulv);
+                    unsigned char *dst = Vt + (8 * cc) * VSB + (hz * YR + hy) * XW + hx;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int sh = 8 * (k & 3);
+                        const unsigned b0 = ((k < 4 ? cv[0].x : cv[0].y) >> sh) & 0xffu;
+                        const unsigned b1 = ((k < 4 ? cv[1].x : cv[1].y) >> sh) & 0xffu;
+                        const unsigned b2 = ((k < 4 ? cv[2].x : cv[2].y) >> sh) & 0xffu;
+                        const unsigned b3 = ((k < 4 ? cv[3].x : cv[3].y) >> sh) & 0xffu;
+                        *(unsigned *)(dst + k * VSB) = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+                    }
+                }
+            }
+        }
+    }
+    // ---- zero the lat rows yn .. YR-1 of every level (read for keys outside
+    // every window, whose weight is 0; 0 x code must stay 0)
+    if (yn < YR) {
+        const int kgap = (YR - yn) * KRS / 4;                 // dwords per level (K)
+        for (int e = tid; e < zn * kgap; e += 256) {
+            const int hz = e / kgap, o = e - hz * kgap;
+            ((unsigned *)(Ks + (hz * YR + yn) * KRS))[o] = 0u;
+        }
+        const int vgap = (YR - yn) * XW / 4;                  // dwords per level and channel (V)
+        for (int e = tid; e < 32 * zn * vgap; e += 256) {
+            const int d = e & 31, col = e >> 5;
+            const int hz = col / vgap, o = col - hz * vgap;
+            ((unsigned *)(Vt + d * VSB + (hz * YR + yn) * XW))[o] = 0u;
+        }
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const int y0g = y0 + 2 * (wave & 1);
+    const int gxa = 2 * (wave >> 1);
+    const int zq = z0 + (r16 >> 2), yq = y0g + ((r16 >> 1) & 1);
+    const int xrel = r16 & 1;
+    const int zc = min(zq, p.Z - 1), yc = min(yq, p.Y - 1);
+
+    int ylg, yng;
+    clamp_range(min(y0g, p.Y - 1), 2, p.Y, KY, ylg, yng);
+    const int dy = ylg - ylo;
+    const int wz = win_start(zc, p.Z, KZ, false) - zlo;
+    const int wy = win_start(yc, p.Y, KY, false) - ylg;
+    const int zb = zlo - zc + KZ - 1;
+    const int yb = ylg - yc + KY - 1;
+    bool oky[2][2];
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            oky[hf][j] = (unsigned)(4 * hf + 2 * j + (g >> 1) - wy) < (unsigned)KY;
+    const int tb_lane = (zb * BY + yb + (g >> 1)) * XT + 4 * (g & 1) - xrel + 1;
+
+    // K fragment (key 16j + r16 = lat row 4hf + 2j + (r16 >> 3), lon column
+    // r16 & 7 of the group halo; channels 8g..8g+7): lane base at level 0.
+    const int kbase = ((r16 >> 3) + dy) * KRS + ((r16 & 7) + GX * gxa) * 32 + 8 * g;
+    // V^T fragment (channel r16; keys 4g..4g+3 of lat row 2j + (g >> 1)):
+    // lane base of group 0 at level 0; group 1 sits 2 bytes further and is
+    // cut out of the same two dwords.
+    const int vbase = r16 * VSB + ((g >> 1) + dy) * XW + 4 * (g & 1) + GX * gxa;
+
+    long qf[2];
+    long qtok[2];
+    bool act[2];
+    const float mulq = q_mul(aq);
+#pragma unroll
+    for (int G = 0; G < 2; ++G) {
+        const int xq = x0 + GX * (gxa + G) + xrel;
+        act[G] = zq < p.Z && yq < p.Y && xq < p.X;
+        const int xc = min(xq, p.X - 1);
+        qtok[G] = ((long)zc * p.Y + yc) * p.X + xc;
+        const uint2 q8 = bf16x8_to_e4m3(*(const uint4 *)(qb + qtok[G] * p.ts + 8 * g), mulq);
+        qf[G] = (long)(((unsigned long long)q8.y << 32) | q8.x);
+    }
+
+    f32x4 oacc[2][2], lacc[2];
+    float mref[2], thr[2], nmc[2];
+    const float tau_raw = TAU / c;
+#pragma unroll
+    for (int G = 0; G < 2; ++G) {
+        oacc[G][0] = oacc[G][1] = lacc[G] = f32x4{0.f, 0.f, 0.f, 0.f};
+        mref[G] = -1e30f;
+        thr[G] = -1e30f;
+        nmc[G] = 0.f;
+    }
+    const long ones = 0x3838383838383838L;   // e4m3 1.0 in every byte
+
+    for (int hz = 0; hz < zn; ++hz) {
+        const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
+        const unsigned char *kz = Ks + kbase + hz * YR * KRS;
+        const unsigned char *vz0 = Vt + vbase + hz * YR * XW;
+        const unsigned char *vz1 = vz0 + 16 * VSB;
+        const int tbh = tb_lane + hz * BY * XT;
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            f32x4 binit[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int a = (okz && oky[hf][j]) ? tbh : TBL;
+                const float *tp = tbl + a + (4 * hf + 2 * j) * XT;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) binit[j][i] = tp[i];
+            }
+            f32x4 s[2][2];
+            float cm[2];
+#pragma unroll
+            for (int G = 0; G < 2; ++G)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const long kf = *(const long *)(kz + (4 * hf + 2 * j) * KRS + GX * 32 * G);
+                    s[G][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(kf, qf[G], binit[j], 0, 0, 0);
+                }
+#pragma unroll
+            for (int G = 0; G < 2; ++G)
+                cm[G] = fmaxf(fmaxf(fmaxf(s[G][0][0], s[G][0][1]), fmaxf(s[G][0][2], s[G][0][3])),
+                              fmaxf(fmaxf(s[G][1][0], s[G][1][1]), fmaxf(s[G][1][2], s[G][1][3])));
+            if (__builtin_amdgcn_ballot_w64(cm[0] > thr[0] || cm[1] > thr[1])) {
+#pragma unroll
+                for (int G = 0; G < 2; ++G) {
+                    const float mn = fmaxf(mref[G], xmax16_32(cm[G]));
+                    const float al = __builtin_amdgcn_exp2f(c * (mref[G] - mn));
+                    mref[G] = mn;
+                    thr[G] = mn + tau_raw;
+                    nmc[G] = -c * mn;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        oacc[G][0][i] *= al;
+                        oacc[G][1][i] *= al;
+                        lacc[G][i] *= al;
+                    }
+                }
+            }
+            long pf[2];
+#pragma unroll
+            for (int G = 0; G < 2; ++G) {
+                float pv[8];
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) pv[4 * j + i] = __builtin_amdgcn_exp2f(fmaf(s[G][j][i], c, nmc[G]));
+                unsigned lo = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(pv[0], pv[1], 0, false);
+                lo = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(pv[2], pv[3], (int)lo, true);
+                unsigned hi = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(pv[4], pv[5], 0, false);
+                hi = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(pv[6], pv[7], (int)hi, true);
+                pf[G] = (long)(((unsigned long long)hi << 32) | lo);
+            }
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt) {
+                const unsigned char *vz = tt ? vz1 : vz0;
+                const unsigned d0 = *(const unsigned *)(vz + (4 * hf) * XW);
+                const unsigned d1 = *(const unsigned *)(vz + (4 * hf) * XW + 4);
+                const unsigned d2 = *(const unsigned *)(vz + (4 * hf + 2) * XW);
+                const unsigned d3 = *(const unsigned *)(vz + (4 * hf + 2) * XW + 4);
+                const long v0 = (long)(((unsigned long long)d2 << 32) | d0);
+                const long v1 = (long)(((unsigned long long)__builtin_amdgcn_alignbyte(d3, d2, 2) << 32) |
+                                       __builtin_amdgcn_alignbyte(d1, d0, 2));
+                oacc[0][tt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(v0, pf[0], oacc[0][tt], 0, 0, 0);
+                oacc[1][tt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(v1, pf[1], oacc[1][tt], 0, 0, 0);
+            }
+#pragma unroll
+            for (int G = 0; G < 2; ++G)
+                lacc[G] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ones, pf[G], lacc[G], 0, 0, 0);
+        }
+    }
+
+    const float sv = dq_scale(av);
+#pragma unroll
+    for (int G = 0; G < 2; ++G) {
+        if (!act[G]) continue;
+        const float inv = sv / lacc[G][0];
+        bf16 *ob = (bf16 *)p.out + (size_t)b * p.obs + (size_t)qtok[G] * p.ots + h * 32;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            f32x4 v = oacc[G][tt];
+            uint2 u;
+            u.x = (unsigned)f2bf_bits(v[0] * inv) | ((unsigned)f2bf_bits(v[1] * inv) << 16);
+            u.y = (unsigned)f2bf_bits(v[2] * inv) | ((unsigned)f2bf_bits(v[3] * inv) << 16);
+            *(uint2 *)(ob + 16 * tt + 4 * g) = u;
+        }
+    }
+}
+
 // Largest halo extent of a clamped axis over the tiles of size tsize.
 int max_halo(int N, int K, int tsize) {
     int m = 0;
@@ -425,8 +772,34 @@ hipError_t launch_tile_q(const NatArgs &a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+size_t tile_lds_fp8(int Kz, int Ky, int zw, int yr) {
+    const int tblp = (((2 * Kz - 1) * (2 * Ky - 1) * XT + NEG_RUN + 3) & ~3);
+    return (size_t)tblp * 4 + (size_t)zw * yr * KRS + 32 * (size_t)vt_row_bytes(zw, yr);
+}
+
+template <int KZ, int KY, int KX>
+hipError_t launch_tile_fp8(const NatArgs &a, hipStream_t stream) {
+    const int zw = max_halo(a.Z, KZ, TZ), yr = std::max(max_halo(a.Y, KY, TY), YR_MIN);
+    const size_t lds = tile_lds_fp8(KZ, KY, zw, yr);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)nat_tile_fp8_kernel<KZ, KY, KX>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    constexpr int TBLP = tbl_padded<KZ, KY, KX>();
+    nat_bias_prep_fp8<KZ, KY, KX><<<(a.B * a.H * TBLP + 255) / 256, 256, 0, stream>>>(a);
+    const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
+    const long total = (long)ntiles * a.H * a.B;
+    const unsigned grid = (unsigned)(((total + 7) >> 3) << 3);
+    nat_tile_fp8_kernel<KZ, KY, KX><<<grid, 256, lds, stream>>>(a, zw, yr);
+    return hipGetLastError();
+}
+
 template <int KZ, int KY, int KX>
 hipError_t launch_tile(const NatArgs &a, hipStream_t stream) {
+    if (a.amax) return launch_tile_fp8<KZ, KY, KX>(a, stream);
     if (a.qscale == 1.0f) return launch_tile_q<KZ, KY, KX, true>(a, stream);
     return launch_tile_q<KZ, KY, KX, false>(a, stream);
 }
@@ -442,7 +815,8 @@ size_t nat_tile_lds_bytes(const NatArgs &a) {
     if (!a.tbl_ws) return 0;
     // K is addressed with 32-bit byte offsets from the state's base
     if ((long)a.Z * a.Y * a.X * a.ts * 2 >= (1L << 31)) return 0;
-    return tile_lds(a.Kz, a.Ky, max_halo(a.Z, a.Kz, TZ), std::max(max_halo(a.Y, a.Ky, TY), YR_MIN));
+    const int zw = max_halo(a.Z, a.Kz, TZ), yr = std::max(max_halo(a.Y, a.Ky, TY), YR_MIN);
+    return a.amax ? tile_lds_fp8(a.Kz, a.Ky, zw, yr) : tile_lds(a.Kz, a.Ky, zw, yr);
 }
 
 hipError_t launch_nat_tile(const NatArgs &a, hipStream_t stream) {

@@ -57,6 +57,12 @@ hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, Ep
 // any copy, launch_amax_fold reduces slots [0, n) into copy 0.
 constexpr int AMAX_SHARDS = 64;
 constexpr int AMAX_STRIDE = 512;            // slots per copy (>= 8 per state x 64 states)
+// per-state amax of bf16 data: state b covers elements [b*per_state, (b+1)*per_state);
+// atomicMax into amax[shard*AMAX_STRIDE + b*amax_stride] (fold afterwards)
+hipError_t launch_amax_bf16(const void *x, size_t per_state, int B, unsigned *amax, int amax_stride,
+                            hipStream_t stream);
+// zero n 32-bit words (a kernel, so graph capture records no memset node)
+hipError_t launch_zero_u32(unsigned *p, size_t n, hipStream_t stream);
 hipError_t launch_amax_fold(unsigned *amax, int n, hipStream_t stream);
 // Two-pass LayerNorm: per-state amax of the LN output (atomicMax into
 // amax[state], which the caller zeroes), then LN + quantize.
@@ -80,7 +86,13 @@ struct NatArgs {
     int B, Z, Y, X, H;
     int Kz, Ky, Kx;
     unsigned periodic;
-    float *tbl_ws;          // device scratch of NAT_TBL_WS_FLOATS * H floats (tiled kernel)
+    float *tbl_ws;          // device scratch of NAT_TBL_WS_FLOATS * H floats (tiled kernel;
+                            // B * H tables for the FP8 variant)
+    // FP8 attention: per-state amax of q, k, v (floats at amax[b*amax_stride
+    // + 0, 1, 2]); when set and the tiled kernel applies, both contractions
+    // run on e4m3 codes with the scales amax/448.
+    const float *amax;
+    int amax_stride;
 };
 constexpr int NAT_TBL_WS_FLOATS = 2048;     // per head, >= padded bias table
 // Picks the LDS-tiled bf16 kernel when it applies, else the generic one.

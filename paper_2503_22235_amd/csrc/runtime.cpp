@@ -15,7 +15,7 @@ size_t block_workspace_bytes(const wm_processor *p, int B) {
     if (p->prec == WM_FP8_E4M3) {
         // u8/w8 | qkv or h (bf16) | o (bf16) | h8 | bias tables | amax slots
         return al256(M * C) + al256(M * std::max(3 * C, F) * 2) + al256(M * C * 2) + al256(M * F) +
-               (size_t)p->g.heads * NAT_TBL_WS_FLOATS * 4 + (size_t)AMAX_SHARDS * AMAX_STRIDE * 4;
+               (size_t)B * p->g.heads * NAT_TBL_WS_FLOATS * 4 + (size_t)AMAX_SHARDS * AMAX_STRIDE * 4;
     }
     const size_t esz = p->prec == WM_BF16 ? 2 : 4;
     const size_t big = (3 * C > F ? 3 * C : F);
@@ -130,8 +130,10 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
 // FP8 block: LayerNorms quantize their outputs per state (two passes), the
 // QKV and MLP GEMMs run on e4m3 operands (per-tensor weight scales, per-state
 // activation scales), the QKV and MLP1 epilogues record per-state amax of
-// their bf16 outputs, the GELU output is quantized before MLP2; attention and
-// the output projection run in bf16; the residual stream stays float32.
+// their bf16 outputs; attention quantizes Q, K and V with those per-state
+// scales and runs QK and PV on e4m3 (weights with the static scale 1); the
+// GELU output is quantized before MLP2; the output projection runs in bf16;
+// softmax, LayerNorm statistics and the residual stream stay float32.
 static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s) {
     const wm_grid &g = p->g;
     const BlockWeights &w = p->blk[block];
@@ -144,7 +146,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     char *obuf = big + al256((size_t)M * std::max(3 * C, F) * 2);
     unsigned char *h8 = (unsigned char *)(obuf + al256((size_t)M * C * 2));
     float *tbl_ws = (float *)((char *)h8 + al256((size_t)M * F));
-    unsigned *amax = (unsigned *)((char *)tbl_ws + (size_t)H * NAT_TBL_WS_FLOATS * 4);
+    unsigned *amax = (unsigned *)((char *)tbl_ws + (size_t)B * H * NAT_TBL_WS_FLOATS * 4);
     unsigned *amax_u = amax, *amax_qkv = amax + B, *amax_w = amax + 4 * B, *amax_h = amax + 5 * B;
     hipError_t e;
     int rc;
@@ -153,7 +155,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
     if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
     if (B > 64) return fail(WM_EINVAL, "FP8 processors take at most 64 states per call");
-    if ((e = hipMemsetAsync(amax, 0, (size_t)AMAX_SHARDS * AMAX_STRIDE * 4, s)) != hipSuccess)
+    if ((e = launch_zero_u32(amax, (size_t)AMAX_SHARDS * AMAX_STRIDE, s)) != hipSuccess)
         return hip_fail(e, "amax reset");
     WM_TIMED(PK_LN1, launch_layernorm_fp8(x, w.ln1_g, w.ln1_b, M, C, (int)T, 1e-5f, amax_u, act8, s), "LN1")
     EpiArgs ep{};
@@ -186,6 +188,8 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     na.B = B; na.Z = g.Z; na.Y = g.Y; na.X = g.X; na.H = H;
     na.Kz = g.Kz; na.Ky = g.Ky; na.Kx = g.Kx; na.periodic = g.periodic_mask;
     na.tbl_ws = tbl_ws;
+    na.amax = (const float *)amax_qkv;
+    na.amax_stride = 3;
     WM_TIMED(PK_NA, launch_nat(na, true, s), "NA")
     EpiArgs er{};
     er.bias = w.b_o;
