@@ -121,8 +121,13 @@ def serve_run(wm, np, S, ctx, g, p6, p1, n_req, rate, max_batch, seed=3):
     out = np.empty(x0.shape, np.float32)
     t0 = time.perf_counter()
     nxt = 0
+    t_log = 0.0
     while nxt < n_req or pending:
         now = time.perf_counter() - t0
+        if now - t_log > 20.0:
+            t_log = now
+            print(f"bench: serving {now:.0f} s: {len(stats)}/{n_req} done, {len(pending)} in flight",
+                  file=sys.stderr, flush=True)
         while nxt < n_req and arrivals[nxt] <= now:
             rid = wm.wm_serve_submit(srv, x0, int(leads[nxt]))
             pending[rid] = nxt
@@ -381,12 +386,13 @@ def main():
         log("fp8 timed region (4 states)")
         x4 = torch.from_numpy(x0).cuda()
         k8 = max(2, args.steps // 2)
-        dt8, _ = time_steps(wm, torch, ctx, p8, x4, 4, k8, 1)
+        dt8, prof8 = time_steps(wm, torch, ctx, p8, x4, 4, k8, 1, profile=True)
         xb = torch.from_numpy(x0[:1].copy()).cuda()
         dt81, _ = time_steps(wm, torch, ctx, p8, xb, 1, k8, 1)
         out["fp8"] = {"batch": 4, "state_steps_per_s": round(4 * k8 / dt8, 3),
                       "ms_per_batch_step": round(dt8 / k8 * 1e3, 2),
-                      "b1_steps_per_s": round(k8 / dt81, 3)}
+                      "b1_steps_per_s": round(k8 / dt81, 3),
+                      "kernels_us_b4": {k: round(ms / n * 1e3, 1) for k, (ms, n) in prof8.items() if n}}
         p8.close()
 
     if not args.no_cpu_baseline:

@@ -325,8 +325,11 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
             *dst = (const float *)(dev + off);
             off += n * 4;
         };
-        // source [in][out] -> device [out][in]; returns the fp8 dequant scale
-        auto put_wt = [&](const float *s, int in, int outn, const void **dst, bool q8) -> float {
+        // source [in][out] -> device [out][in] (bf16 and e4m3 with pr: rows
+        // permuted within groups of 32 by perm_row); returns the fp8 dequant
+        // scale
+        auto put_wt = [&](const float *s, int in, int outn, const void **dst, bool q8, bool pr) -> float {
+            auto src_col = [&](int o) { return pr ? perm_row(o) : o; };
             off = align(off);
             if (q8) {
                 float amax = 0.f;
@@ -334,7 +337,8 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
                 const float inv = amax > 0.f ? 448.0f / amax : 1.0f;
                 unsigned char *d = img.data() + off;
                 for (int o = 0; o < outn; ++o)
-                    for (int i = 0; i < in; ++i) d[(size_t)o * in + i] = host_fp8_e4m3(s[(size_t)i * outn + o] * inv);
+                    for (int i = 0; i < in; ++i)
+                        d[(size_t)o * in + i] = host_fp8_e4m3(s[(size_t)i * outn + src_col(o)] * inv);
                 *dst = dev + off;
                 off += (size_t)in * outn;
                 return amax > 0.f ? amax / 448.0f : 1.0f;
@@ -342,7 +346,7 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
             if (esz == 2) {
                 uint16_t *d = (uint16_t *)(img.data() + off);
                 for (int o = 0; o < outn; ++o)
-                    for (int i = 0; i < in; ++i) d[(size_t)o * in + i] = host_bf16(s[(size_t)i * outn + o]);
+                    for (int i = 0; i < in; ++i) d[(size_t)o * in + i] = host_bf16(s[(size_t)i * outn + src_col(o)]);
             } else {
                 float *d = (float *)(img.data() + off);
                 for (int o = 0; o < outn; ++o)
@@ -374,10 +378,12 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
         put_vec(ln2_b, C, 1.f, &bw.ln2_b);
         put_vec(b_1, F, 1.f, &bw.b_1);
         put_vec(b_2, C, 1.f, &bw.b_2);
-        bw.dq_qkv = put_wt(w_qkv, C, 3 * C, &bw.w_qkv, fp8);
-        put_wt(w_o, C, C, &bw.w_o, false);
-        bw.dq_1 = put_wt(w_1, C, F, &bw.w_1, fp8);
-        bw.dq_2 = put_wt(w_2, F, C, &bw.w_2, fp8);
+        // QKV and MLP1 rows permuted (their epilogues store 8 features per
+        // lane); the residual GEMMs keep the natural order
+        bw.dq_qkv = put_wt(w_qkv, C, 3 * C, &bw.w_qkv, fp8, true);
+        put_wt(w_o, C, C, &bw.w_o, false, false);
+        bw.dq_1 = put_wt(w_1, C, F, &bw.w_1, fp8, true);
+        bw.dq_2 = put_wt(w_2, F, C, &bw.w_2, fp8, false);
         if ((e = hipMemcpy(dev, img.data(), blk_bytes, hipMemcpyHostToDevice)) != hipSuccess) {
             (void)hipFree(p->mem);
             delete p;

@@ -21,6 +21,7 @@
 // activation tile, so every lane ends up with four consecutive output
 // features of one token for the epilogue.  Tiles go out in an XCD-aware
 // order (consecutive ids on one XCD share an activation tile in its L2).
+#include <algorithm>
 #include <cstdlib>
 
 #include "kernels.hpp"
@@ -61,15 +62,14 @@ __device__ __forceinline__ void store4(bf16 *p, f32x4 v) {
 // of the tile's part, `hc` the channel within the part and `qs` the Q scale
 // (1 for K and V): all but hc are uniform over the tile.
 template <int EPI>
-__device__ __forceinline__ float epilogue4(const EpiArgs &ep, int M, int N, int m, int n, f32x4 v,
+__device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int n, f32x4 v,
                                            size_t qkv_base, int hc, float qs, float dq) {
-    if (m >= M) return 0.f;
     v[0] *= dq; v[1] *= dq; v[2] *= dq; v[3] *= dq;
     const float4 b = *(const float4 *)(ep.bias + n);
     v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
     if constexpr (EPI == EPI_QKV) {
         v[0] *= qs; v[1] *= qs; v[2] *= qs; v[3] *= qs;
-        store4((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * M + m) * 32 + (hc & 31), v);
+        store4((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * ep.Mtot + m) * 32 + (hc & 31), v);
     } else if constexpr (EPI == EPI_GELU) {
         v[0] = gelu_as(v[0]); v[1] = gelu_as(v[1]); v[2] = gelu_as(v[2]); v[3] = gelu_as(v[3]);
         store4((bf16 *)ep.out + (size_t)m * N + n, v);
@@ -82,6 +82,50 @@ __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int M, int N, int 
         store4((bf16 *)ep.out + (size_t)m * N + n, v);
     }
     return fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
+}
+
+__device__ __forceinline__ void store8(bf16 *p, const float *v) {
+    uint4 u;
+    u.x = (unsigned)f2bf_bits(v[0]) | ((unsigned)f2bf_bits(v[1]) << 16);
+    u.y = (unsigned)f2bf_bits(v[2]) | ((unsigned)f2bf_bits(v[3]) << 16);
+    u.z = (unsigned)f2bf_bits(v[4]) | ((unsigned)f2bf_bits(v[5]) << 16);
+    u.w = (unsigned)f2bf_bits(v[6]) | ((unsigned)f2bf_bits(v[7]) << 16);
+    *(uint4 *)p = u;
+}
+
+// Epilogue on eight consecutive output features n..n+7 of (global) token
+// mg, from two MFMA tiles of permuted W rows (16-byte stores; 32 bytes for
+// the float32 residual).  Same conventions as epilogue4.
+template <int EPI>
+__device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, int n, f32x4 a, f32x4 c,
+                                           size_t qkv_base, int hc, float qs, float dq) {
+    float v[8] = {a[0], a[1], a[2], a[3], c[0], c[1], c[2], c[3]};
+    const float4 b0 = *(const float4 *)(ep.bias + n), b1 = *(const float4 *)(ep.bias + n + 4);
+    const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = v[i] * dq + bb[i];
+    if constexpr (EPI == EPI_QKV) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] *= qs;
+        store8((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * ep.Mtot + mg) * 32 + (hc & 31), v);
+    } else if constexpr (EPI == EPI_GELU) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = gelu_as(v[i]);
+        store8((bf16 *)ep.out + (size_t)mg * N + n, v);
+    } else if constexpr (EPI == EPI_RESID) {
+        float4 *r = (float4 *)(ep.resid + (size_t)mg * N + n);
+        float4 x0 = r[0], x1 = r[1];
+        x0.x += v[0]; x0.y += v[1]; x0.z += v[2]; x0.w += v[3];
+        x1.x += v[4]; x1.y += v[5]; x1.z += v[6]; x1.w += v[7];
+        r[0] = x0;
+        r[1] = x1;
+    } else {
+        store8((bf16 *)ep.out + (size_t)mg * N + n, v);
+    }
+    float m = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
+    return m;
 }
 
 // s_waitcnt with vmcnt <= n and no wait on the other counters (gfx9 encoding:
@@ -237,27 +281,40 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         const int n0 = (tn0 + t) * BN;
         // a feature tile never straddles Q/K/V (C is a multiple of BN)
         const int part = EPI == EPI_QKV ? n0 / ep.C : 0;
-        const size_t qkv_base = (size_t)part * ep.H * M * 32;
+        const size_t qkv_base = (size_t)part * ep.H * ep.Mtot * 32;
         const float qs = part == 0 ? ep.qscale : 1.0f;
         // per-row dequantization (fp8) and per-state amax of the outputs
         float dq[TM];
         int srow[TM];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
-            const int m = min(m0 + wm * WM + 16 * i + r16, M - 1);
-            srow[i] = FP8 || ep.out_amax ? (int)(m / ep.T) : 0;
+            const long mg = (long)min(m0 + wm * WM + 16 * i + r16, M - 1) + ep.row0;
+            srow[i] = FP8 || ep.out_amax ? (int)(mg / ep.T) : 0;
             dq[i] = FP8 ? ep.a_amax[srow[i]] * (1.0f / 448.0f) * ep.w_dequant : 1.0f;
         }
-        const int s_lo = ep.out_amax ? (int)(min(m0, M - 1) / ep.T) : 0;
+        const int s_lo = ep.out_amax ? (int)(((long)min(m0, M - 1) + ep.row0) / ep.T) : 0;
         float mlo = 0.f, mhi = 0.f;
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < TN; j += 2)
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
                 const int m = m0 + wm * WM + 16 * i + r16;
-                const int n = n0 + wn * WN + 16 * j + 4 * g;
-                const float a = epilogue4<EPI>(ep, M, N, m, n, acc[j][i], qkv_base, n - part * ep.C, qs, dq[i]);
+                const long mg = (long)m + ep.row0;
+                float a = 0.f;
+                if (m < M) {
+                    if (ep.perm) {
+                        const int n = n0 + wn * WN + 16 * j + 8 * g;
+                        a = epilogue8<EPI>(ep, N, mg, n, acc[j][i], acc[j + 1][i], qkv_base, n - part * ep.C, qs,
+                                           dq[i]);
+                    } else {
+                        const int n = n0 + wn * WN + 16 * j + 4 * g;
+                        a = fmaxf(epilogue4<EPI>(ep, N, mg, n, acc[j][i], qkv_base, n - part * ep.C, qs, dq[i]),
+                                  epilogue4<EPI>(ep, N, mg, n + 16, acc[j + 1][i], qkv_base, n + 16 - part * ep.C,
+                                                 qs, dq[i]));
+                    }
+                }
                 acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+                acc[j + 1][i] = f32x4{0.f, 0.f, 0.f, 0.f};
                 if (ep.out_amax) {
                     if (srow[i] == s_lo) mlo = fmaxf(mlo, a);
                     else if (srow[i] == s_lo + 1) mhi = fmaxf(mhi, a);
@@ -272,7 +329,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
             if (lane == 0) {
                 unsigned *sh = ep.out_amax + (blockIdx.x % AMAX_SHARDS) * AMAX_STRIDE;
                 atomicMax(sh + s_lo * ep.amax_stride + part, __float_as_uint(mlo));
-                if ((long)(s_lo + 1) * ep.T < M)
+                if ((long)(s_lo + 1) * ep.T < (long)ep.Mtot)
                     atomicMax(sh + (s_lo + 1) * ep.amax_stride + part, __float_as_uint(mhi));
             }
         }
@@ -306,23 +363,36 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
     }();
     const int tpw_req = tpw_env > 0 ? tpw_env : tpw_default;
     const int tpw = tpw_req < ntn ? tpw_req : ntn;
-    const int total = ((ntn + tpw - 1) / tpw) * ((M + BM - 1) / BM);
-    const int grid = ((total + 7) >> 3) << 3;
-    switch (epi) {
-    case EPI_QKV:
-        gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8><<<grid, NTH, lds, stream>>>(A, W, M, N, K, ep, tpw);
-        break;
-    case EPI_GELU:
-        gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8><<<grid, NTH, lds, stream>>>(A, W, M, N, K, ep, tpw);
-        break;
-    case EPI_RESID:
-        gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8><<<grid, NTH, lds, stream>>>(A, W, M, N, K, ep, tpw);
-        break;
-    default:
-        gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8><<<grid, NTH, lds, stream>>>(A, W, M, N, K, ep, tpw);
-        break;
+    // A is addressed with 32-bit byte offsets from the chunk's first row:
+    // split M into row chunks below 2 GiB of A.
+    const size_t row_bytes = (size_t)K * (FP8 ? 1 : 2);
+    const int chunk = (int)std::min<size_t>((size_t)M, ((size_t)0x7fffffff / row_bytes) / BM * BM);
+    for (int r0 = 0; r0 < M; r0 += chunk) {
+        const int Mc = std::min(chunk, M - r0);
+        EpiArgs e = ep;
+        e.row0 = r0;
+        e.Mtot = M;
+        const void *Ac = (const unsigned char *)A + (size_t)r0 * row_bytes;
+        const int total = ((ntn + tpw - 1) / tpw) * ((Mc + BM - 1) / BM);
+        const int grid = ((total + 7) >> 3) << 3;
+        switch (epi) {
+        case EPI_QKV:
+            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw);
+            break;
+        case EPI_GELU:
+            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw);
+            break;
+        case EPI_RESID:
+            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw);
+            break;
+        default:
+            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw);
+            break;
+        }
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace glds
@@ -330,8 +400,8 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
 using namespace glds;
 
 bool gemm_lds_applies(int M, int N, int K) {
-    return N % 128 == 0 && K % 64 == 0 && (unsigned long long)M * K * 2 < (1ull << 32) &&
-           (unsigned long long)N * K * 2 < (1ull << 32);
+    (void)M;
+    return N % 128 == 0 && K % 64 == 0 && (unsigned long long)N * K * 2 < (1ull << 31);
 }
 
 hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
@@ -361,7 +431,7 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
 hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                            hipStream_t stream) {
     if (M <= 0) return hipSuccess;
-    if (N % 128 || K % 128 || (unsigned long long)M * K >= (1ull << 32)) return hipErrorInvalidValue;
+    if (N % 128 || K % 128 || (unsigned long long)N * K >= (1ull << 31)) return hipErrorInvalidValue;
     static const int cfg = [] {
         const char *v = getenv("WM_GEMM_CFG");
         return v ? atoi(v) : -1;

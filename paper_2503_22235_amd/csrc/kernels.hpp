@@ -36,7 +36,21 @@ struct EpiArgs {
     // state * amax_stride + (QKV part or 0)
     unsigned *out_amax;
     int amax_stride;
+    // W rows permuted within aligned groups of 32 (perm_row), so a lane's
+    // two adjacent MFMA tiles hold 8 consecutive output features and store
+    // them at once; set for processor weights, not for caller-supplied W
+    // (LDS GEMMs only).
+    int perm;
+    // Set by the LDS GEMM launchers when they split M into row chunks: the
+    // global row of the chunk's row 0 and the total row count.
+    int row0, Mtot;
 };
+// Output feature stored in W row o when EpiArgs.perm is set: within each
+// group of 32 rows, row 16 jj + 4 g + i holds feature 8 g + 4 jj + i.
+__host__ __device__ inline int perm_row(int o) {
+    const int r = o & 31, jj = r >> 4, rho = r & 15;
+    return (o & ~31) + 8 * (rho >> 2) + 4 * jj + (rho & 3);
+}
 // A: [M][K], W: [N][K], both bf16 (a_bf16) or float32.  Output element
 // type follows the operands (bf16 or float) except EPI_RESID (float32).
 // Requires N % 128 == 0 (N % 64 for small N) and K % 64 == 0 (bf16) /

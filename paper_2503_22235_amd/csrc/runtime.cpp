@@ -89,6 +89,7 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     ep.C = C;
     ep.H = H;
     ep.qscale = LOG2E / std::sqrt(32.0f);
+    ep.perm = bf;   // bf16 W_qkv and W_1 are stored with permuted rows (perm_row)
     WM_TIMED(PK_QKV, launch_gemm(act, w.w_qkv, M, 3 * C, C, bf, EPI_QKV, ep, s), "QKV")
 
     NatArgs na{};
@@ -118,6 +119,7 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     EpiArgs eg{};
     eg.bias = w.b_1;
     eg.out = big;
+    eg.perm = bf;
     WM_TIMED(PK_MLP1, launch_gemm(act, w.w_1, M, F, C, bf, EPI_GELU, eg, s), "MLP1")
     EpiArgs e2{};
     e2.bias = w.b_2;
@@ -169,6 +171,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     ep.T = T;
     ep.out_amax = amax_qkv;
     ep.amax_stride = 3;
+    ep.perm = 1;   // W_qkv and W_1 are stored with permuted rows (perm_row)
     WM_TIMED(PK_QKV, launch_gemm_fp8(act8, w.w_qkv, M, 3 * C, C, EPI_QKV, ep, s), "QKV")
     if ((e = launch_amax_fold(amax_qkv, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
     NatArgs na{};
@@ -204,6 +207,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     eg.T = T;
     eg.out_amax = amax_h;
     eg.amax_stride = 1;
+    eg.perm = 1;
     WM_TIMED(PK_MLP1, launch_gemm_fp8(act8, w.w_1, M, F, C, EPI_GELU, eg, s), "MLP1")
     if ((e = launch_amax_fold(amax_h, B, s)) != hipSuccess) return hip_fail(e, "amax fold");
     WM_TIMED(PK_QUANT, launch_quant_rows(big, M, F, (int)T, (const float *)amax_h, h8, s), "quantize h")

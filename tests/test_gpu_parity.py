@@ -121,6 +121,31 @@ def test_linear(env, prec, epi):
         assert O.rel_l2(got, ref) < tol, (M, N, K)
 
 
+def test_linear_row_chunks(env):
+    """A of more than 2 GiB: the LDS GEMM splits M into row chunks (32-bit
+    buffer offsets); rows on both sides of the first chunk boundary and a
+    seeded sample elsewhere are checked (residual epilogue, bf16)."""
+    wm, torch, ctx = env
+    M, N, K = 140000, 128, 8192
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    a = torch.randn((M, K), generator=gen, device="cuda").to(torch.bfloat16)
+    w = (torch.randn((N, K), generator=gen, device="cuda") / K ** 0.5).to(torch.bfloat16)
+    b = torch.randn(N, generator=gen, device="cuda") * 0.1
+    x0 = torch.randn((M, N), generator=gen, device="cuda")
+    out = x0.clone()
+    say("linear row chunks", M, N, K)
+    wm.wm_linear(M, N, K, wm.WM_BF16, a, w, b, 2, out)
+    chunk = (0x7FFFFFFF // (K * 2)) // 256 * 256
+    rows = np.unique(np.concatenate([[0, chunk - 1, chunk, chunk + 1, M - 1],
+                                     np.random.default_rng(4).choice(M, 60, replace=False)]))
+    rt = torch.from_numpy(rows).cuda()
+    ar = a[rt].double().cpu().numpy()
+    ref = x0[rt].double().cpu().numpy() + ar @ w.double().cpu().numpy().T + b.double().cpu().numpy()
+    got = out[rt].double().cpu().numpy()
+    del a, x0, out
+    assert O.rel_l2(got, ref) < 1e-5
+
+
 # ---------------------------------------------------------------------------
 def _nat_case(env, g, prec, B=1, seed=0, qscale=1.0):
     wm, torch, ctx = env
