@@ -184,9 +184,19 @@ def cpu_baseline(g, params, nblocks=2):
         x = O.block(x, S.split_block_params(g, params, b), g)
     dt = (time.perf_counter() - t0) / nblocks
     del ctxm
+    # the small single-block case (5x45x90, C=128, 4 heads, window 3x5x5) on one thread
+    g1 = S.CFG1
+    p1 = S.processor_params(g1, 1, seed=1)
+    x1 = S.latent_state(g1, 1, seed=0)
+    from threadpoolctl import threadpool_limits   # limits BLAS and the OpenMP loops of the C oracle
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        O.block(x1, S.split_block_params(g1, p1, 0), g1)
+        dt1 = time.perf_counter() - t1
     return {"value": round(1.0 / (8 * dt), 5), "unit": "processor-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{nblocks} of the 8 blocks of one step on the full 8x90x180 grid, FP64 "
-                      f"({dt:.1f} s per block); steps/s = 1/(8 x block time)"}
+                      f"({dt:.1f} s per block); steps/s = 1/(8 x block time)",
+            "small_block_single_thread_s": round(dt1, 3)}
 
 
 KIND_ORDER = ("ln1", "qkv", "nat", "proj", "ln2", "mlp1", "mlp2")
@@ -318,6 +328,11 @@ def main():
     log("bf16 timed region")
     dt, prof = time_steps(wm, torch, ctx, p_bf, x, 1, args.steps, args.warmup, profile=True)
     sps = args.steps / dt
+    reps = []
+    for _ in range(5):   # repeats after the headline region, for the spread
+        d_r, _ = time_steps(wm, torch, ctx, p_bf, x, 1, args.steps, 0)
+        reps.append(args.steps / d_r)
+    reps.sort()
     work = block_kernel_work(g)
     per_kernel = {}
     for k, (ms, n) in prof.items():
@@ -348,6 +363,8 @@ def main():
                    "global_batch": 1, "tokens": g.T, "parallelism": "single-gpu"},
         "roofline": roof,
         "step_mfma_frac": round(flops * sps / (PEAK_BF16_TFLOPS * 1e12), 4),
+        "repeats": {"n": len(reps), "steps_each": args.steps, "median_steps_per_s": round(reps[len(reps) // 2], 3),
+                    "min": round(reps[0], 3), "max": round(reps[-1], 3)},
         "kernels": per_kernel,
     }
 
