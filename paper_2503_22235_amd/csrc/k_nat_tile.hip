@@ -141,40 +141,38 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
     }
     // ---- V halo, transposed: slot (hz, hy, hx) at (hz YR + hy) XW + hx.
-    // Item = (slot pair, 16-byte chunk c), c fastest: 4 lanes read the 2 x 64
-    // contiguous bytes of two neighbouring tokens.  Loads of a batch are
-    // issued before any store (items past the end reload the last item and
-    // are not stored).  Rows yn .. YR-1 of each level are zeroed: the chunk
+    // Item = (slot pair, 16-byte chunk c) of one halo row (level, lat): the
+    // 32 items of a row go to 32 consecutive threads (4 lanes read the 2 x 64
+    // contiguous bytes of two neighbouring tokens), so a thread keeps its lon
+    // pair and chunk and walks rows 8 apart.  Loads of a batch are issued
+    // before any store.  Rows yn .. YR-1 of each level are zeroed: the chunk
     // walk reads them for keys outside every window (weight 0), and 0 x V
     // must stay 0.
     {
-        const int nitems = zn * yn * XW * 2;
-        unsigned *Vt32 = (unsigned *)Vtb;
-        for (int e0 = tid; e0 < nitems; e0 += 256 * LD_BATCH) {
+        const int nrows = zn * yn;
+        const unsigned ym = (65536u + yn - 1) / yn;          // row / yn == (row * ym) >> 16 (row * yn < 2^16)
+        const int c = tid & 3, pr = (tid >> 2) & 7, rb0 = tid >> 5;
+        int xa = xlo + (2 * pr < TX + KX - 1 ? 2 * pr : 0);
+        int xb = xlo + (2 * pr + 1 < TX + KX - 1 ? 2 * pr + 1 : 0);
+        xa = xa < 0 ? xa + p.X : (xa >= p.X ? xa - p.X : xa);
+        xb = xb < 0 ? xb + p.X : (xb >= p.X ? xb - p.X : xb);
+        unsigned *Vt32 = (unsigned *)Vtb + (8 * c) * (VS >> 1) + pr;
+        for (int rb = rb0; rb < nrows; rb += 8 * LD_BATCH) {
             uint4 v0[LD_BATCH], v1[LD_BATCH];
 #pragma unroll
             for (int u = 0; u < LD_BATCH; ++u) {
-                const int e = min(e0 + 256 * u, nitems - 1);
-                const int pr = e >> 2, c = e & 3;
-                const int slot = 2 * pr;                  // even: both slots share the row
-                const int hx = slot % XW, row = slot / XW;
-                const int hy = row % yn, hz = row / yn;
-                int x0c = xlo + (hx < TX + KX - 1 ? hx : 0);
-                int x1c = xlo + (hx + 1 < TX + KX - 1 ? hx + 1 : 0);
-                x0c = x0c < 0 ? x0c + p.X : (x0c >= p.X ? x0c - p.X : x0c);
-                x1c = x1c < 0 ? x1c + p.X : (x1c >= p.X ? x1c - p.X : x1c);
+                const int row = min(rb + 8 * u, nrows - 1);
+                const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
                 const long rtok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X;
-                v0[u] = *(const uint4 *)(vb + (size_t)(rtok + x0c) * p.ts + 8 * c);
-                v1[u] = *(const uint4 *)(vb + (size_t)(rtok + x1c) * p.ts + 8 * c);
+                v0[u] = *(const uint4 *)(vb + (size_t)(rtok + xa) * p.ts + 8 * c);
+                v1[u] = *(const uint4 *)(vb + (size_t)(rtok + xb) * p.ts + 8 * c);
             }
 #pragma unroll
             for (int u = 0; u < LD_BATCH; ++u) {
-                const int e = e0 + 256 * u;
-                if (e < nitems) {
-                    const int pr = e >> 2, c = e & 3;
-                    const int row = (2 * pr) / XW;
-                    const int prs = pr + (row / yn) * (YR - yn) * (XW / 2);   // pair index in the YR layout
-                    unsigned *vrow = Vt32 + (8 * c) * (VS >> 1) + prs;
+                const int row = rb + 8 * u;
+                if (row < nrows) {
+                    const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
+                    unsigned *vrow = Vt32 + (hz * YR + hy) * (XW / 2);
                     vrow[0 * (VS >> 1)] = (v0[u].x & 0xffffu) | (v1[u].x << 16);
                     vrow[1 * (VS >> 1)] = (v0[u].x >> 16) | (v1[u].x & 0xffff0000u);
                     vrow[2 * (VS >> 1)] = (v0[u].y & 0xffffu) | (v1[u].y << 16);
@@ -187,12 +185,13 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
             }
         }
         if (yn < YR) {
+            unsigned *V0 = (unsigned *)Vtb;
             const int gap = (YR - yn) * (XW / 2);              // dword columns per level
             const int nz = zn * gap * 32;
             for (int e = tid; e < nz; e += 256) {
                 const int d = e & 31, col = e >> 5;
                 const int hz = col / gap, cg = col - hz * gap;
-                Vt32[d * (VS >> 1) + (hz * YR + yn) * (XW / 2) + cg] = 0u;
+                V0[d * (VS >> 1) + (hz * YR + yn) * (XW / 2) + cg] = 0u;
             }
         }
     }
@@ -493,75 +492,82 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
         const uint4 *src = (const uint4 *)(p.tbl_ws + ((size_t)b * p.H + h) * TBLP);
         for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
     }
-    // ---- K halo, token-major e4m3: item = (slot, 16-byte chunk c of 8 channels)
+    // ---- K halo, token-major e4m3: item = (slot, 16-byte chunk c of 8
+    // channels); the 64 items of a halo row go to 64 consecutive threads, so
+    // a thread keeps its lon slot and chunk and walks rows 4 apart.
+    const int nrows = zn * yn;
+    const unsigned ym = (65536u + yn - 1) / yn;              // row / yn == (row * ym) >> 16 (row * yn < 2^16)
     {
-        const int nitems = zn * yn * XW * 4;
-        for (int e0 = tid; e0 < nitems; e0 += 256 * LD_BATCH) {
+        const int cc = tid & 3, hx = (tid >> 2) & 15, rb0 = tid >> 6;
+        int xc = xlo + (hx < TX + KX - 1 ? hx : 0);
+        xc = xc < 0 ? xc + p.X : (xc >= p.X ? xc - p.X : xc);
+        unsigned char *kdst = Ks + hx * 32 + 8 * cc;
+        for (int rb = rb0; rb < nrows; rb += 4 * LD_BATCH) {
             uint4 raw[LD_BATCH];
 #pragma unroll
             for (int u = 0; u < LD_BATCH; ++u) {
-                const int e = min(e0 + 256 * u, nitems - 1);
-                const int slot = e >> 2, cc = e & 3;
-                const int hx = slot % XW, row = slot / XW;
-                const int hy = row % yn, hz = row / yn;
-                int xc = xlo + (hx < TX + KX - 1 ? hx : 0);
-                xc = xc < 0 ? xc + p.X : (xc >= p.X ? xc - p.X : xc);
+                const int row = min(rb + 4 * u, nrows - 1);
+                const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
                 const long rtok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X;
                 raw[u] = *(const uint4 *)(kb + (size_t)(rtok + xc) * p.ts + 8 * cc);
             }
 #pragma unroll
             for (int u = 0; u < LD_BATCH; ++u) {
-                const int e = e0 + 256 * u;
-                if (e < nitems) {
-                    const int slot = e >> 2, cc = e & 3;
-                    const int hx = slot % XW, row = slot / XW;
-                    const int hy = row % yn, hz = row / yn;
-                    *(uint2 *)(Ks + (hz * YR + hy) * KRS + hx * 32 + 8 * cc) = bf16x8_to_e4m3(raw[u], mulk);
+                const int row = rb + 4 * u;
+                if (row < nrows) {
+                    const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
+                    *(uint2 *)(kdst + (hz * YR + hy) * KRS) = bf16x8_to_e4m3(raw[u], mulk);
                 }
             }
         }
     }
-    // ---- V halo, transposed e4m3: item = (4 neighbouring slots, chunk c)
+    // ---- V halo, transposed e4m3: item = (4 neighbouring slots, chunk c);
+    // the 16 items of a halo row go to 16 consecutive threads (rows 16 apart).
     {
-        const int nitems = zn * yn * (XW / 4) * 4;
-        for (int e0 = tid; e0 < nitems; e0 += 256 * (LD_BATCH / 2)) {
+        const int cc = tid & 3, qd = (tid >> 2) & 3, rb0 = tid >> 4;
+        int xs[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            int xc = xlo + (4 * qd + w < TX + KX - 1 ? 4 * qd + w : 0);
+            xs[w] = xc < 0 ? xc + p.X : (xc >= p.X ? xc - p.X : xc);
+        }
+        unsigned char *vdst = Vt + (8 * cc) * VSB + 4 * qd;
+        for (int rb = rb0; rb < nrows; rb += 16 * (LD_BATCH / 2)) {
             uint4 raw[LD_BATCH / 2][4];
 #pragma unroll
             for (int u = 0; u < LD_BATCH / 2; ++u) {
-                const int e = min(e0 + 256 * u, nitems - 1);
-                const int qd = e >> 2, cc = e & 3;
-                const int slot = 4 * qd;
-                const int hx = slot % XW, row = slot / XW;
-                const int hy = row % yn, hz = row / yn;
+                const int row = min(rb + 16 * u, nrows - 1);
+                const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
                 const long rtok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X;
 #pragma unroll
-                for (int w = 0; w < 4; ++w) {
-                    int xc = xlo + (hx + w < TX + KX - 1 ? hx + w : 0);
-                    xc = xc < 0 ? xc + p.X : (xc >= p.X ? xc - p.X : xc);
-                    raw[u][w] = *(const uint4 *)(vb + (size_t)(rtok + xc) * p.ts + 8 * cc);
-                }
+                for (int w = 0; w < 4; ++w) raw[u][w] = *(const uint4 *)(vb + (size_t)(rtok + xs[w]) * p.ts + 8 * cc);
             }
 #pragma unroll
             for (int u = 0; u < LD_BATCH / 2; ++u) {
-                const int e = e0 + 256 * u;
-                if (e < nitems) {
-                    const int qd = e >> 2, cc = e & 3;
-                    const int slot = 4 * qd;
-                    const int hx = slot % XW, row = slot / XW;
-                    const int hy = row % yn, hz = row / yn;
+                const int row = rb + 16 * u;
+                if (row < nrows) {
+                    const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
                     uint2 cv[4];
 #pragma unroll
                     for (int w = 0; w < 4; ++w) cv[w] = bf16x8_to_e4m3(raw[u][w], mulv);
-                    unsigned char *dst = Vt + (8 * cc) * VSB + (hz * YR + hy) * XW + hx;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int sh = 8 * (k & 3);
-                        const unsigned b0 = ((k < 4 ? cv[0].x : cv[0].y) >> sh) & 0xffu;
-                        const unsigned b1 = ((k < 4 ? cv[1].x : cv[1].y) >> sh) & 0xffu;
-                        const unsigned b2 = ((k < 4 ? cv[2].x : cv[2].y) >> sh) & 0xffu;
-                        const unsigned b3 = ((k < 4 ? cv[3].x : cv[3].y) >> sh) & 0xffu;
-                        *(unsigned *)(dst + k * VSB) = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
-                    }
+                    // 4 tokens x 8 channels of bytes -> 8 dwords of 4 tokens each
+                    const unsigned lo01 = __builtin_amdgcn_perm(cv[1].x, cv[0].x, 0x05010400u);  // t0c0 t1c0 t0c1 t1c1
+                    const unsigned lo23 = __builtin_amdgcn_perm(cv[3].x, cv[2].x, 0x05010400u);
+                    const unsigned hi01 = __builtin_amdgcn_perm(cv[1].x, cv[0].x, 0x07030602u);  // c2, c3
+                    const unsigned hi23 = __builtin_amdgcn_perm(cv[3].x, cv[2].x, 0x07030602u);
+                    const unsigned lo01b = __builtin_amdgcn_perm(cv[1].y, cv[0].y, 0x05010400u);
+                    const unsigned lo23b = __builtin_amdgcn_perm(cv[3].y, cv[2].y, 0x05010400u);
+                    const unsigned hi01b = __builtin_amdgcn_perm(cv[1].y, cv[0].y, 0x07030602u);
+                    const unsigned hi23b = __builtin_amdgcn_perm(cv[3].y, cv[2].y, 0x07030602u);
+                    unsigned char *dst = vdst + (hz * YR + hy) * XW;
+                    *(unsigned *)(dst + 0 * VSB) = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+                    *(unsigned *)(dst + 1 * VSB) = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+                    *(unsigned *)(dst + 2 * VSB) = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+                    *(unsigned *)(dst + 3 * VSB) = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+                    *(unsigned *)(dst + 4 * VSB) = __builtin_amdgcn_perm(lo23b, lo01b, 0x05040100u);
+                    *(unsigned *)(dst + 5 * VSB) = __builtin_amdgcn_perm(lo23b, lo01b, 0x07060302u);
+                    *(unsigned *)(dst + 6 * VSB) = __builtin_amdgcn_perm(hi23b, hi01b, 0x05040100u);
+                    *(unsigned *)(dst + 7 * VSB) = __builtin_amdgcn_perm(hi23b, hi01b, 0x07060302u);
                 }
             }
         }
