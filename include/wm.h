@@ -88,6 +88,10 @@ void wm_ctx_destroy(wm_ctx *ctx);
  * projection, LN2, MLP1, MLP2, FP8 quantization of the MLP hidden state;
  * arrays of nkinds entries, either may be NULL) and clears the records. */
 int wm_prof_enable(wm_ctx *ctx, int on);
+/* Like wm_prof_enable, for the kinds whose bit is set in kinds_mask only
+ * (bit k = kind k; 0 turns timing off), so that a timed region carries
+ * events around the kernels it reports and no others. */
+int wm_prof_select(wm_ctx *ctx, unsigned kinds_mask);
 int wm_prof_collect(wm_ctx *ctx, double *ms, long long *counts, int nkinds);
 
 /* Neighborhood index tables of a grid (Sec. 2.1 NATTEN; App. A.2).

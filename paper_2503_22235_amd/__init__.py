@@ -18,7 +18,7 @@ __all__ = [
     "wm_nat_forward", "wm_layernorm", "wm_linear", "wm_processor_create",
     "wm_processor_destroy", "wm_processor_block", "wm_processor_step",
     "wm_schedule", "wm_rollout", "wm_relerr_l2", "grid_of", "LIB_PATH",
-    "wm_prof_enable", "wm_prof_collect", "PROF_KINDS", "wm_serve_create",
+    "wm_prof_enable", "wm_prof_select", "wm_prof_collect", "PROF_KINDS", "wm_serve_create",
     "wm_serve_submit", "wm_serve_poll", "wm_serve_status", "wm_serve_destroy",
     "wm_quantize_fp8", "wm_linear_fp8",
 ]
@@ -82,6 +82,7 @@ _SIGS = {
     "wm_rollout": (_int, [_vp, _vp, _vp, _int, _vp, _int, _vp]),
     "wm_relerr_l2": (ctypes.c_double, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "wm_prof_enable": (_int, [_vp, _int]),
+    "wm_prof_select": (_int, [_vp, ctypes.c_uint]),
     "wm_serve_create": (_int, [_vp, _vp, _vp, ctypes.POINTER(wm_serve_cfg), ctypes.POINTER(_vp)]),
     "wm_serve_submit": (_int, [_vp, _vp, _int, ctypes.POINTER(ctypes.c_uint64)]),
     "wm_serve_poll": (_int, [_vp, ctypes.c_uint64, _vp, ctypes.POINTER(wm_req_stats)]),
@@ -252,6 +253,14 @@ def wm_linear_fp8(M, N, K, a8, a_dequant, w8, w_dequant, bias, epilogue, out, st
 
 def wm_prof_enable(ctx, on=True):
     return _check(lib().wm_prof_enable(ctx.handle, 1 if on else 0))
+
+
+def wm_prof_select(ctx, kinds):
+    """Time only the given kinds (names from PROF_KINDS)."""
+    mask = 0
+    for k in kinds:
+        mask |= 1 << PROF_KINDS.index(k)
+    return _check(lib().wm_prof_select(ctx.handle, mask))
 
 
 def wm_prof_collect(ctx):

@@ -122,7 +122,13 @@ void wm_ctx_destroy(wm_ctx *ctx) {
 
 int wm_prof_enable(wm_ctx *ctx, int on) {
     if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
-    ctx->prof = on != 0;
+    ctx->prof_mask = on != 0 ? 0xffffffffu : 0u;
+    return WM_OK;
+}
+
+int wm_prof_select(wm_ctx *ctx, unsigned kinds_mask) {
+    if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
+    ctx->prof_mask = kinds_mask;
     return WM_OK;
 }
 

@@ -40,17 +40,19 @@ static hipEvent_t pool_get(wm_ctx *ctx) {
 }
 
 int prof_begin(wm_ctx *ctx, hipStream_t s, int kind) {
-    if (!ctx->prof) return WM_OK;
+    if (!((ctx->prof_mask >> kind) & 1u)) return WM_OK;
     ProfRec r{kind, pool_get(ctx), pool_get(ctx)};
     if (!r.a || !r.b) return fail(WM_EHIP, "hipEventCreate failed");
     hipError_t e = hipEventRecord(r.a, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     ctx->recs.push_back(r);
+    ctx->prof_open = true;
     return WM_OK;
 }
 
 int prof_end(wm_ctx *ctx, hipStream_t s) {
-    if (!ctx->prof || ctx->recs.empty()) return WM_OK;
+    if (!ctx->prof_open || ctx->recs.empty()) return WM_OK;
+    ctx->prof_open = false;
     hipError_t e = hipEventRecord(ctx->recs.back().b, s);
     return e == hipSuccess ? WM_OK : hip_fail(e, "hipEventRecord");
 }

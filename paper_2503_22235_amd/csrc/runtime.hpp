@@ -37,7 +37,8 @@ struct wm_ctx {
     void *ws = nullptr;       // block intermediates, grown on demand
     size_t ws_bytes = 0;
     void *small = nullptr;    // 4 KiB of device scratch (reductions)
-    bool prof = false;        // bracket every block kernel with HIP events
+    unsigned prof_mask = 0;   // bracket block kernels of these kinds (bit k = kind k) with HIP events
+    bool prof_open = false;   // a record is waiting for its end event
     std::vector<wm::ProfRec> recs;
     std::vector<hipEvent_t> pool;
 };
@@ -60,7 +61,7 @@ int ctx_reserve(wm_ctx *ctx, size_t bytes);
 // Bytes of workspace a block of processor p needs for B states.
 size_t block_workspace_bytes(const wm_processor *p, int B);
 int reserve_block_workspace(wm_ctx *ctx, const wm_processor *p, int B);
-// Timing records (no-ops unless ctx->prof).
+// Timing records (no-ops for kinds outside ctx->prof_mask).
 int prof_begin(wm_ctx *ctx, hipStream_t s, int kind);
 int prof_end(wm_ctx *ctx, hipStream_t s);
 // Enqueue one block / one step on `s` (workspace already reserved).
