@@ -250,6 +250,22 @@ int wm_serve_status(wm_server *s, int *queued, int *running, int *done, int *slo
  * the server's memory. */
 void wm_serve_destroy(wm_server *s);
 
+/* Every hourly lead 1..hours of one state, sharing prefixes (Sec. 2.1:
+ * hourly outputs from the six-hour and one-hour processors).  The six-hour
+ * chain runs once; each one-hour branch starts from the six-hour state
+ * before it, so lead L comes from the same steps, in the same order, as
+ * wm_rollout(L): floor(L/6) six-hour steps, then L mod 6 one-hour steps --
+ * about 56 + 280 = 336 steps for 336 hours instead of 10136 for separate
+ * rollouts.  Branches of up to `batch` (1..64) six-hour states run as one
+ * batched one-hour step.
+ * x: device float32 state [Z*Y*X*C] (B = 1), not modified.  outs: host
+ * array of `hours` device pointers (float32 [Z*Y*X*C] each, caller-owned);
+ * outs[L-1] receives the state at lead L; a NULL entry (or outs == NULL)
+ * skips that lead.  Keeps 1 + batch state copies in context memory.  Work
+ * is enqueued on `stream`. */
+int wm_forecast_hourly(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1, const float *x,
+                       int hours, float *const *outs, int batch, void *stream);
+
 /* Relative L2 error ||y - y_ref|| / ||y_ref|| of n values, accumulated in
  * float64 on the GPU.  y: device float32; y_ref: device float64.  Waits
  * for the stream and returns the value (negative on error). */

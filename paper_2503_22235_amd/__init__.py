@@ -17,7 +17,7 @@ __all__ = [
     "wm_version", "wm_ctx_create", "wm_ctx_destroy", "wm_nat_indices",
     "wm_nat_forward", "wm_layernorm", "wm_linear", "wm_processor_create",
     "wm_processor_destroy", "wm_processor_block", "wm_processor_step",
-    "wm_schedule", "wm_rollout", "wm_relerr_l2", "grid_of", "LIB_PATH",
+    "wm_schedule", "wm_rollout", "wm_forecast_hourly", "wm_relerr_l2", "grid_of", "LIB_PATH",
     "wm_prof_enable", "wm_prof_select", "wm_prof_collect", "PROF_KINDS", "wm_serve_create",
     "wm_serve_submit", "wm_serve_poll", "wm_serve_status", "wm_serve_destroy",
     "wm_quantize_fp8", "wm_linear_fp8",
@@ -80,6 +80,7 @@ _SIGS = {
     "wm_processor_step": (_int, [_vp, _vp, _int, _vp, _vp]),
     "wm_schedule": (_int, [_int, ctypes.POINTER(_int), _int]),
     "wm_rollout": (_int, [_vp, _vp, _vp, _int, _vp, _int, _vp]),
+    "wm_forecast_hourly": (_int, [_vp, _vp, _vp, _vp, _int, _vp, _int, _vp]),
     "wm_relerr_l2": (ctypes.c_double, [_vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "wm_prof_enable": (_int, [_vp, _int]),
     "wm_prof_select": (_int, [_vp, ctypes.c_uint]),
@@ -240,6 +241,18 @@ def wm_schedule(lead_hours: int):
 def wm_rollout(ctx, p6, p1, B, x, lead_hours, stream=None):
     return _check(lib().wm_rollout(ctx.handle, p6.handle, p1.handle, B, _ptr(x), lead_hours,
                                    _stream(stream)))
+
+
+def wm_forecast_hourly(ctx, p6, p1, x, hours, outs=None, batch=8, stream=None):
+    """outs: None or a sequence of `hours` device tensors / None entries
+    (outs[L-1] receives the state at lead L)."""
+    arr = None
+    if outs is not None:
+        if len(outs) != hours:
+            raise ValueError("outs must have one entry per hour")
+        arr = (ctypes.c_void_p * hours)(*[(_ptr(o) if o is not None else None) for o in outs])
+    return _check(lib().wm_forecast_hourly(ctx.handle, p6.handle, p1.handle, _ptr(x), hours, arr, batch,
+                                           _stream(stream)))
 
 
 def wm_quantize_fp8(x, mul, out, stream=None):

@@ -117,6 +117,7 @@ void wm_ctx_destroy(wm_ctx *ctx) {
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->small) (void)hipFree(ctx->small);
+    if (ctx->aux) (void)hipFree(ctx->aux);
     delete ctx;
 }
 
@@ -459,6 +460,78 @@ int wm_rollout(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1, int 
         rc = run_step(ctx, s == 6 ? p6 : p1, B, x, (hipStream_t)stream);
         if (rc) return rc;
     }
+    return WM_OK;
+}
+
+int wm_forecast_hourly(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1, const float *x, int hours,
+                       float *const *outs, int batch, void *stream) {
+    if (!ctx || !p6 || !p1) return fail(WM_EINVAL, "NULL ctx or processor");
+    if (hours < 0) return fail(WM_EINVAL, "negative hours %d", hours);
+    if (batch < 1 || batch > 64) return fail(WM_EINVAL, "batch must be in 1..64");
+    if (std::memcmp(&p6->g, &p1->g, sizeof(wm_grid)) != 0) return fail(WM_EINVAL, "processors have different grids");
+    if (hours == 0) return WM_OK;
+    if (!x) return fail(WM_EINVAL, "x is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)p6->g.Z * p6->g.Y * p6->g.X * p6->g.C;
+    const size_t sb = n * 4;
+    int rc = reserve_block_workspace(ctx, p6, 1);
+    if (rc) return rc;
+    rc = reserve_block_workspace(ctx, p1, batch);
+    if (rc) return rc;
+    // aux: the six-hour chain state, then `batch` branch states
+    const size_t need = sb * (size_t)(1 + batch);
+    if (need > ctx->aux_bytes) {
+        hipError_t e;
+        if (ctx->aux) {
+            if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+            (void)hipFree(ctx->aux);
+            ctx->aux = nullptr;
+            ctx->aux_bytes = 0;
+        }
+        if ((e = hipMalloc(&ctx->aux, need)) != hipSuccess) {
+            ctx->aux = nullptr;
+            (void)hipGetLastError();
+            return fail(WM_ENOMEM, "forecast states (%zu bytes): %s", need, hipGetErrorString(e));
+        }
+        ctx->aux_bytes = need;
+    }
+    float *chain = (float *)ctx->aux;
+    float *branch = chain + n;
+    hipError_t e;
+    auto copy = [&](float *dst, const float *src) -> int {
+        if ((e = hipMemcpyAsync(dst, src, sb, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+            return hip_fail(e, "state copy");
+        return WM_OK;
+    };
+    auto out_of = [&](int lead) -> float * { return outs && lead >= 1 && lead <= hours ? outs[lead - 1] : nullptr; };
+    if ((rc = copy(chain, x))) return rc;
+    int base[64], nbr = 0;
+    // One-hour branches of the gathered six-hour states: j steps give leads base + j.
+    auto run_branches = [&]() -> int {
+        int jmax = 0;
+        for (int i = 0; i < nbr; ++i) jmax = std::max(jmax, std::min(5, hours - base[i]));
+        for (int j = 1; j <= jmax; ++j) {
+            if ((rc = run_step(ctx, p1, nbr, branch, s))) return rc;
+            for (int i = 0; i < nbr; ++i)
+                if (float *o = base[i] + j <= hours ? out_of(base[i] + j) : nullptr)
+                    if ((rc = copy(o, branch + (size_t)i * n))) return rc;
+        }
+        nbr = 0;
+        return WM_OK;
+    };
+    for (int lead = 0; lead <= hours; lead += 6) {
+        if (lead > 0) {
+            if ((rc = run_step(ctx, p6, 1, chain, s))) return rc;
+            if (float *o = out_of(lead))
+                if ((rc = copy(o, chain))) return rc;
+        }
+        if (lead + 1 <= hours) {
+            if ((rc = copy(branch + (size_t)nbr * n, chain))) return rc;
+            base[nbr++] = lead;
+            if (nbr == batch && (rc = run_branches())) return rc;
+        }
+    }
+    if (nbr > 0 && (rc = run_branches())) return rc;
     return WM_OK;
 }
 

@@ -37,6 +37,8 @@ struct wm_ctx {
     void *ws = nullptr;       // block intermediates, grown on demand
     size_t ws_bytes = 0;
     void *small = nullptr;    // 4 KiB of device scratch (reductions)
+    void *aux = nullptr;      // state copies of the hourly forecast, grown on demand
+    size_t aux_bytes = 0;
     unsigned prof_mask = 0;   // bracket block kernels of these kinds (bit k = kind k) with HIP events
     bool prof_open = false;   // a record is waiting for its end event
     std::vector<wm::ProfRec> recs;

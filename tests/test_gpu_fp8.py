@@ -195,3 +195,23 @@ def test_nat_fp8_exact_when_weights_are_equal(env):
     err = np.abs(got[0] - ref).max()
     say(f"fp8 nat equal weights: max abs error {err:.2e}")
     assert err <= 2.0 ** -8 * 2.0 + 1e-6      # one bf16 rounding of a value of magnitude <= 2
+
+
+def test_fp8_block_batch_17_row_chunks(env):
+    """17 states at 8x90x180: the e4m3 GEMM operands exceed 2 GiB, so the
+    GEMMs run in row chunks; the last state's result must equal its result
+    alone (per-state scales, bit for bit)."""
+    wm, torch, ctx = env
+    g = S.CFG2
+    params = S.processor_params(g, 1, 1)
+    B = 17
+    p = wm.wm_processor_create(ctx, g, 1, 4, wm.WM_FP8_E4M3, params)
+    xb = torch.empty((B,) + (g.Z, g.Y, g.X, g.C), device="cuda")
+    for b in range(B):
+        xb[b] = torch.from_numpy(S.latent_state(g, 1, seed=0, index0=b)[0]).cuda()
+    x1 = xb[B - 1:B].clone()
+    say("fp8 block batch", B)
+    wm.wm_processor_block(ctx, p, 0, B, xb)
+    wm.wm_processor_block(ctx, p, 0, 1, x1)
+    assert torch.equal(xb[B - 1:B], x1)
+    p.close()

@@ -336,3 +336,52 @@ def test_relerr_gpu_fp64(env):
     y = (ref + 1e-3 * r.standard_normal(ref.shape)).astype(np.float32)
     got = wm.wm_relerr_l2(ctx, torch.from_numpy(y).cuda(), torch.from_numpy(ref).cuda())
     assert abs(got - O.rel_l2(y, ref)) < 1e-12
+
+
+def test_empty_and_degenerate_calls(env):
+    """B = 0 and M = 0 calls are no-ops; a rollout to lead 0 leaves the state
+    unchanged bit for bit; a one-hour rollout equals one one-hour step."""
+    wm, torch, ctx = env
+    g = S.CFG1
+    p6 = wm.wm_processor_create(ctx, g, 1, 4, wm.WM_BF16, S.processor_params(g, 1, 1, proc=0))
+    p1 = wm.wm_processor_create(ctx, g, 1, 4, wm.WM_BF16, S.processor_params(g, 1, 2, proc=1))
+    x0 = torch.from_numpy(S.latent_state(g, 1, 0)).cuda()
+    empty = torch.empty(0, device="cuda")
+    wm.wm_processor_step(ctx, p6, 0, empty)
+    wm.wm_nat_forward(ctx, g, 0, wm.WM_BF16, empty, empty, empty, empty, empty)
+    wm.wm_layernorm(0, g.C, empty, empty, empty, 1e-5, wm.WM_BF16, empty)
+    wm.wm_linear(0, 128, 128, wm.WM_BF16, empty, empty, empty, 0, empty)
+    x = x0.clone()
+    wm.wm_rollout(ctx, p6, p1, 1, x, 0)
+    assert torch.equal(x, x0)
+    y = x0.clone()
+    wm.wm_rollout(ctx, p6, p1, 1, x, 1)
+    wm.wm_processor_step(ctx, p1, 1, y)
+    assert torch.equal(x, y)
+    p6.close()
+    p1.close()
+
+
+@pytest.mark.parametrize("batch", [1, 3, 8])
+def test_forecast_hourly_equals_rollouts(env, batch):
+    """Every hourly lead of the prefix-sharing forecast equals the rollout
+    to that lead bit for bit (same steps in the same order; one-hour
+    branches batched), for 1..17 h (2 full six-hour bases and a partial
+    last branch)."""
+    wm, torch, ctx = env
+    g = S.CFG1
+    p6 = wm.wm_processor_create(ctx, g, 2, 4, wm.WM_BF16, S.processor_params(g, 2, 1, proc=0))
+    p1 = wm.wm_processor_create(ctx, g, 2, 4, wm.WM_BF16, S.processor_params(g, 2, 2, proc=1))
+    x0 = torch.from_numpy(S.latent_state(g, 1, 0)[0]).cuda()
+    hours = 17
+    outs = [torch.full_like(x0, float("nan")) for _ in range(hours)]
+    outs[4] = None                                   # a skipped lead
+    wm.wm_forecast_hourly(ctx, p6, p1, x0, hours, outs, batch=batch)
+    for lead in range(1, hours + 1):
+        if outs[lead - 1] is None:
+            continue
+        y = x0.clone()
+        wm.wm_rollout(ctx, p6, p1, 1, y, lead)
+        assert torch.equal(outs[lead - 1], y), lead
+    p6.close()
+    p1.close()
