@@ -49,7 +49,7 @@ __all__ = [
     "window_axis", "neighbor_ids", "neighborhood_attention", "nat_at",
     "layer_norm", "gelu", "block", "block_at", "processor_step",
     "schedule", "rollout", "rel_l2", "nat_c", "oracle_threads",
-    "e4m3_values", "e4m3_encode", "e4m3_decode",
+    "e4m3_values", "e4m3_encode", "e4m3_decode", "rope_angles", "apply_rope",
 ]
 
 LN_EPS = 1e-5
@@ -235,6 +235,48 @@ def _p64(p):
     return {k: np.asarray(v, np.float64) for k, v in p.items()}
 
 
+# ---------------------------------------------------------------------------
+# Rotary position embedding (App. A.2 names rotary embeddings, after
+# RoFormer, without the 3-D details).  Reading: axial RoPE on the d = 32
+# channels of a head, as 16 pairs of neighbouring channels (2i, 2i+1);
+# pairs 0-3 rotate with the level index z, pairs 4-9 with the latitude
+# index y, pairs 10-15 with the longitude index x.  Level and latitude use
+# the RoFormer frequency ladder 10000^(-j/P) (j = 0..P-1, P pairs of the
+# axis); longitude uses the integer frequencies 2 pi (j+1) / X so that its
+# rotation is periodic on the circle, like the lon windows.  q and k are
+# rotated, v is not.
+# ---------------------------------------------------------------------------
+ROPE_PAIRS = ((0, 4), (4, 6), (10, 6))          # (first pair, pairs) for z, y, x
+
+
+def rope_angles(g, tokens=None):
+    """Rotation angle of every pair at each token: [n, 16] float64."""
+    if g.d != 32:
+        raise ValueError("rotary layout is defined for d = 32")
+    tokens = np.arange(g.T) if tokens is None else np.asarray(tokens, np.int64)
+    pos = (tokens // (g.Y * g.X), (tokens // g.X) % g.Y, tokens % g.X)
+    ang = np.zeros((tokens.shape[0], 16))
+    for axis, (p0, n) in enumerate(ROPE_PAIRS):
+        j = np.arange(n)
+        if axis == 2:
+            w = 2.0 * math.pi * (j + 1) / g.X
+        else:
+            w = 10000.0 ** (-j / n)
+        ang[:, p0:p0 + n] = pos[axis][:, None] * w[None, :]
+    return ang
+
+
+def apply_rope(t, ang):
+    """Rotate the channel pairs of t [n, H, 32] by ang [n, 16]."""
+    t = np.asarray(t, np.float64)
+    c, s = np.cos(ang)[:, None, :], np.sin(ang)[:, None, :]
+    a, b = t[..., 0::2], t[..., 1::2]
+    out = np.empty_like(t)
+    out[..., 0::2] = a * c - b * s
+    out[..., 1::2] = a * s + b * c
+    return out
+
+
 def _qkv_heads(u, p, g):
     qkv = u @ p["w_qkv"] + p["b_qkv"]
     C, H, d = g.C, g.heads, g.d
@@ -249,13 +291,14 @@ def _mlp_half(x1, p):
     return x1 + gelu(w @ p["w_1"] + p["b_1"]) @ p["w_2"] + p["b_2"]
 
 
-def block(x, p, g):
+def block(x, p, g, rope=False):
     """One pre-norm neighborhood-attention transformer block.
 
     x: [B, Z, Y, X, C] (or [Z, Y, X, C]); p: dict of one block's parameters
     (canonical names of ``wm_synth.block_param_layout``).
       u  = LN1(x)
       q, k, v = u W_qkv + b_qkv, split into heads (channel = head*d + e)
+      (rope: q and k rotated by their token's angles, ``apply_rope``)
       o  = neighborhood attention with relative-position bias
       x1 = x + o W_o + b_o
       x2 = x1 + GELU(LN2(x1) W_1 + b_1) W_2 + b_2
@@ -271,6 +314,9 @@ def block(x, p, g):
         xb = x[b].reshape(g.T, g.C)
         u = layer_norm(xb, p["ln1_g"], p["ln1_b"])
         q, k, v = _qkv_heads(u, p, g)
+        if rope:
+            ang = rope_angles(g)
+            q, k = apply_rope(q, ang), apply_rope(k, ang)
         o = _nat_any(q, k, v, p["rpb"], g).reshape(g.T, g.C)
         x1 = xb + o @ p["w_o"] + p["b_o"]
         out[b] = _mlp_half(x1, p).reshape(g.Z, g.Y, g.X, g.C)
@@ -292,7 +338,7 @@ def nat_at(q, k, v, rpb, g, tokens):
     return o
 
 
-def block_at(x, p, g, tokens):
+def block_at(x, p, g, tokens, rope=False):
     """Block output of one state at the given tokens only.
 
     x: [Z, Y, X, C] (or [T, C]).  Every token's output depends on its own
@@ -307,6 +353,9 @@ def block_at(x, p, g, tokens):
                           return_inverse=True)
     u = layer_norm(np.asarray(xf[need], np.float64), p["ln1_g"], p["ln1_b"])
     q, k, v = _qkv_heads(u, p, g)
+    if rope:
+        ang = rope_angles(g, need)
+        q, k = apply_rope(q, ang), apply_rope(k, ang)
     n = tokens.shape[0]
     qi = inv[:n]
     ki = inv[n:].reshape(ids.shape)
@@ -316,10 +365,10 @@ def block_at(x, p, g, tokens):
     return _mlp_half(x1, p)
 
 
-def processor_step(x, params_blocks, g):
+def processor_step(x, params_blocks, g, rope=False):
     """One processor step: its blocks applied in order (Sec. 2.1)."""
     for p in params_blocks:
-        x = block(x, p, g)
+        x = block(x, p, g, rope)
     return x
 
 

@@ -400,3 +400,65 @@ def test_e4m3_table_and_rounding():
     r = np.random.default_rng(0).standard_normal(10000) * 50
     back = O.e4m3_decode(O.e4m3_encode(r))
     assert np.all(np.abs(back - np.clip(r, -448, 448)) <= np.maximum(np.abs(r) * 2.0 ** -4, 2.0 ** -10) + 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Rotary position embedding (the paper's encoding; its 3-D layout is a
+# reading, see the oracle).  Pinned by what rotary embeddings must satisfy.
+
+def _tok(g, z, y, x):
+    return (np.asarray(z) * g.Y + np.asarray(y)) * g.X + np.asarray(x)
+
+
+def test_rope_identity_at_origin_and_norms():
+    g = S.Grid(Z=4, Y=9, X=12, C=64, heads=2, Kz=3, Ky=3, Kx=3)
+    r = np.random.default_rng(0)
+    t = r.standard_normal((g.T, 2, 32))
+    ang = O.rope_angles(g)
+    out = O.apply_rope(t, ang)
+    assert np.array_equal(out[0], t[0])                      # token (0, 0, 0): no rotation
+    pair_norm = lambda a: a[..., 0::2] ** 2 + a[..., 1::2] ** 2
+    assert np.allclose(pair_norm(out), pair_norm(t), rtol=1e-13, atol=0)
+
+
+def test_rope_scores_depend_on_offsets_only():
+    """R(p) q . R(p') k is unchanged when both positions move by the same
+    offset: any lon shift (with wrap: integer frequencies), lat and level
+    shifts that stay on the grid."""
+    g = S.Grid(Z=6, Y=15, X=20, C=32, heads=1, Kz=3, Ky=3, Kx=3)
+    r = np.random.default_rng(1)
+    q = r.standard_normal((1, 1, 32))
+    k = r.standard_normal((1, 1, 32))
+
+    def score(tq, tk):
+        aq = O.rope_angles(g, [tq])
+        ak = O.rope_angles(g, [tk])
+        return float(np.sum(O.apply_rope(q, aq) * O.apply_rope(k, ak)))
+
+    for _ in range(40):
+        zq, zk = r.integers(0, 3, 2)
+        yq, yk = r.integers(0, 8, 2)
+        xq, xk = r.integers(0, g.X, 2)
+        dz, dy, dx = r.integers(0, 3), r.integers(0, 7), r.integers(-40, 40)
+        s0 = score(_tok(g, zq, yq, xq), _tok(g, zk, yk, xk))
+        s1 = score(_tok(g, zq + dz, yq + dy, (xq + dx) % g.X), _tok(g, zk + dz, yk + dy, (xk + dx) % g.X))
+        assert abs(s0 - s1) < 1e-11 * (1 + abs(s0))
+    # and it does depend on the offset
+    assert abs(score(_tok(g, 0, 0, 0), _tok(g, 0, 0, 1)) - score(_tok(g, 0, 0, 0), _tok(g, 0, 0, 2))) > 1e-6
+
+
+def test_block_rope_wiring_and_lon_roll():
+    g = S.Grid(Z=3, Y=7, X=10, C=64, heads=2, Kz=3, Ky=3, Kx=5)
+    p = S.split_block_params(g, S.processor_params(g, 1, seed=5), 0)
+    x = S.latent_state(g, 1, seed=6)[0].astype(np.float64)
+    # q = k = 0 (zero W_q, W_k and their biases): rotating them changes nothing
+    pz = {k_: np.array(v, np.float64) for k_, v in p.items()}
+    pz["w_qkv"][:, :2 * g.C] = 0.0
+    pz["b_qkv"][:2 * g.C] = 0.0
+    assert np.array_equal(O.block(x, pz, g, rope=True), O.block(x, pz, g, rope=False))
+    # with rotary q and k the block still commutes with a lon roll
+    y = O.block(x, p, g, rope=True)
+    yr = O.block(np.roll(x, 3, axis=2), p, g, rope=True)
+    assert np.abs(yr - np.roll(y, 3, axis=2)).max() < 1e-10
+    # and differs from the block without rotation
+    assert np.abs(y - O.block(x, p, g, rope=False)).max() > 1e-6
