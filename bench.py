@@ -387,6 +387,13 @@ def main():
     if args.copy_probe_mib:
         copy_probe(torch, args.copy_probe_mib)
 
+    # ---- the same processor with rotary q/k (the paper's position encoding)
+    wm.wm_processor_set_rope(p_bf, True)
+    x.copy_(torch.from_numpy(x0[:1].copy()))
+    dtr, _ = time_steps(wm, torch, ctx, p_bf, x, 1, args.steps, 1)
+    out["bf16_rope"] = {"steps_per_s": round(args.steps / dtr, 3), "ms_per_step": round(dtr / args.steps * 1e3, 3)}
+    wm.wm_processor_set_rope(p_bf, False)
+
     # ---- hourly 14-day forecast (prefix sharing: 56 six-hour + 280 one-hour steps)
     p1_bf = wm.wm_processor_create(ctx, g, nb, 4, wm.WM_BF16, S.processor_params(g, nb, seed=2, proc=1))
     if not args.no_hourly:

@@ -177,6 +177,17 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks,
                         int mlp_ratio, wm_precision prec,
                         const float *host_params, wm_processor **out);
 void wm_processor_destroy(wm_processor *p);
+/* Rotary position embedding for this processor's blocks (App. A.2 uses
+ * rotary embeddings; the 3-D layout is this library's reading): q and k of
+ * every head are rotated in the QKV epilogue, channel pairs (2i, 2i+1) with
+ * pairs 0-3 following the level index z at angles z * 10000^(-i/4), pairs
+ * 4-9 the latitude index y at y * 10000^(-(i-4)/6), pairs 10-15 the
+ * longitude index x at x * 2 pi (i-9) / X (periodic in lon).  The
+ * relative-position bias still applies: a processor created with zero bias
+ * tables is a pure rotary one.  on = 0 turns it off.  Allocates a small
+ * device table on first use; not to be called while the processor runs. */
+int wm_processor_set_rope(wm_processor *p, int on);
+
 int wm_processor_blocks(const wm_processor *p);
 
 /* One block, in place on x (device float32 [B][Z][Y][X][C]):

@@ -16,7 +16,7 @@ __all__ = [
     "WM_F32", "WM_BF16", "WM_FP8_E4M3", "WmError", "wm_grid", "lib",
     "wm_version", "wm_ctx_create", "wm_ctx_destroy", "wm_nat_indices",
     "wm_nat_forward", "wm_layernorm", "wm_linear", "wm_processor_create",
-    "wm_processor_destroy", "wm_processor_block", "wm_processor_step",
+    "wm_processor_destroy", "wm_processor_block", "wm_processor_step", "wm_processor_set_rope",
     "wm_schedule", "wm_rollout", "wm_forecast_hourly", "wm_relerr_l2", "grid_of", "LIB_PATH",
     "wm_prof_enable", "wm_prof_select", "wm_prof_collect", "PROF_KINDS", "wm_serve_create",
     "wm_serve_submit", "wm_serve_poll", "wm_serve_status", "wm_serve_destroy",
@@ -76,6 +76,7 @@ _SIGS = {
     "wm_processor_create": (_int, [_vp, ctypes.POINTER(wm_grid), _int, _int, _int, _vp, ctypes.POINTER(_vp)]),
     "wm_processor_destroy": (None, [_vp]),
     "wm_processor_blocks": (_int, [_vp]),
+    "wm_processor_set_rope": (_int, [_vp, _int]),
     "wm_processor_block": (_int, [_vp, _vp, _int, _int, _vp, _vp]),
     "wm_processor_step": (_int, [_vp, _vp, _int, _vp, _vp]),
     "wm_schedule": (_int, [_int, ctypes.POINTER(_int), _int]),
@@ -221,6 +222,10 @@ def wm_processor_create(ctx, grid, n_blocks, mlp_ratio, prec, host_params) -> Pr
 
 def wm_processor_destroy(p: Processor):
     p.close()
+
+
+def wm_processor_set_rope(p, on=True):
+    return _check(lib().wm_processor_set_rope(p.handle, 1 if on else 0))
 
 
 def wm_processor_block(ctx, p, block, B, x, stream=None):

@@ -406,7 +406,51 @@ void wm_processor_destroy(wm_processor *p) {
     (void)hipSetDevice(p->device);
     (void)hipDeviceSynchronize();
     if (p->mem) (void)hipFree(p->mem);
+    if (p->rope_tab) (void)hipFree(p->rope_tab);
     delete p;
+}
+
+int wm_processor_set_rope(wm_processor *p, int on) {
+    if (!p) return fail(WM_EINVAL, "processor is NULL");
+    hipError_t e;
+    if ((e = hipSetDevice(p->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (!on) {
+        if (p->rope_tab) {
+            if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+            (void)hipFree(p->rope_tab);
+            p->rope_tab = nullptr;
+        }
+        return WM_OK;
+    }
+    if (p->rope_tab) return WM_OK;
+    const int Z = p->g.Z, Y = p->g.Y, X = p->g.X, rows = Z + Y + X;
+    // angle of pair q at position pos of its axis: level pairs 0-3 and lat
+    // pairs 4-9 on the frequency ladder 10000^(-j/P), lon pairs 10-15 at
+    // the integer frequencies 2 pi (j+1) / X
+    std::vector<float> tab((size_t)rows * 16 * 2);
+    for (int r = 0; r < rows; ++r) {
+        const int axis = r < Z ? 0 : (r < Z + Y ? 1 : 2);
+        const int pos = axis == 0 ? r : (axis == 1 ? r - Z : r - Z - Y);
+        for (int q = 0; q < 16; ++q) {
+            double ang = 0.0;
+            if (axis == 0 && q < 4) ang = pos * std::pow(10000.0, -q / 4.0);
+            else if (axis == 1 && q >= 4 && q < 10) ang = pos * std::pow(10000.0, -(q - 4) / 6.0);
+            else if (axis == 2 && q >= 10) ang = pos * 2.0 * M_PI * (q - 10 + 1) / X;
+            tab[((size_t)r * 16 + q) * 2] = (float)std::cos(ang);
+            tab[((size_t)r * 16 + q) * 2 + 1] = (float)std::sin(ang);
+        }
+    }
+    float *d = nullptr;
+    if ((e = hipMalloc(&d, tab.size() * 4)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(WM_ENOMEM, "rotary table: %s", hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(d, tab.data(), tab.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "rotary table copy");
+    }
+    p->rope_tab = d;
+    return WM_OK;
 }
 
 int wm_processor_blocks(const wm_processor *p) { return p ? p->nb : fail(WM_EINVAL, "processor is NULL"); }

@@ -44,6 +44,11 @@ __device__ __forceinline__ void epilogue4(const EpiArgs &ep, int M, int N, int m
         const int part = n / ep.C;
         const int hc = n - part * ep.C;
         const int h = hc >> 5, e = hc & 31;
+        if (ep.rope && part < 2) {
+            float r[4] = {v[0], v[1], v[2], v[3]};
+            rope_rotate(r, 4, e, m, ep);
+            v[0] = r[0]; v[1] = r[1]; v[2] = r[2]; v[3] = r[3];
+        }
         if (part == 0) { v[0] *= ep.qscale; v[1] *= ep.qscale; v[2] *= ep.qscale; v[3] *= ep.qscale; }
         TO *dst = (TO *)ep.out + (((size_t)(part * ep.H + h) * M + m) * 32 + e);
         store4(dst, v);

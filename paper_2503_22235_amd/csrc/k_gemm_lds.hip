@@ -68,6 +68,11 @@ __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int
     const float4 b = *(const float4 *)(ep.bias + n);
     v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
     if constexpr (EPI == EPI_QKV) {
+        if (ep.rope && n < 2 * ep.C) {
+            float r[4] = {v[0], v[1], v[2], v[3]};
+            rope_rotate(r, 4, hc & 31, m, ep);
+            v[0] = r[0]; v[1] = r[1]; v[2] = r[2]; v[3] = r[3];
+        }
         v[0] *= qs; v[1] *= qs; v[2] *= qs; v[3] *= qs;
         store4((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * ep.Mtot + m) * 32 + (hc & 31), v);
     } else if constexpr (EPI == EPI_GELU) {
@@ -105,6 +110,7 @@ __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, in
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = v[i] * dq + bb[i];
     if constexpr (EPI == EPI_QKV) {
+        if (ep.rope && n < 2 * ep.C) rope_rotate(v, 8, hc & 31, mg, ep);
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] *= qs;
         store8((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * ep.Mtot + mg) * 32 + (hc & 31), v);

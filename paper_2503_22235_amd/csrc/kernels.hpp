@@ -41,10 +41,33 @@ struct EpiArgs {
     // them at once; set for processor weights, not for caller-supplied W
     // (LDS GEMMs only).
     int perm;
+    // EPI_QKV with rotary position embedding: table of (cos, sin) per
+    // [axis offset + position][pair] (level rows 0..Z-1, lat rows Z..Z+Y-1,
+    // lon rows Z+Y..Z+Y+X-1; 16 pairs; see rope_rotate) and the grid; null: none
+    const float *rope;
+    int rZ, rY, rX;
     // Set by the LDS GEMM launchers when they split M into row chunks: the
     // global row of the chunk's row 0 and the total row count.
     int row0, Mtot;
 };
+// Rotary position embedding of cnt consecutive channels e.. (e even) of a
+// q or k head row at global row mg (token mg mod T): channel pair p =
+// e/2 + i rotates by the angle of its axis (pairs 0-3 level, 4-9 lat, 10-15
+// lon) at the token's position, read from the (cos, sin) table.
+__device__ __forceinline__ void rope_rotate(float *v, int cnt, int e, long mg, const EpiArgs &ep) {
+    const unsigned t = (unsigned)(mg % ep.T);
+    const unsigned yx = (unsigned)(ep.rY * ep.rX);
+    const int z = (int)(t / yx), y = (int)((t / (unsigned)ep.rX) % (unsigned)ep.rY), x = (int)(t % (unsigned)ep.rX);
+    for (int i = 0; i < cnt / 2; ++i) {
+        const int p = e / 2 + i;
+        const int row = p < 4 ? z : (p < 10 ? ep.rZ + y : ep.rZ + ep.rY + x);
+        const float2 cs = *(const float2 *)(ep.rope + 2 * (row * 16 + p));
+        const float a = v[2 * i], b = v[2 * i + 1];
+        v[2 * i] = a * cs.x - b * cs.y;
+        v[2 * i + 1] = a * cs.y + b * cs.x;
+    }
+}
+
 // Output feature stored in W row o when EpiArgs.perm is set: within each
 // group of 32 rows, row 16 jj + 4 g + i holds feature 8 g + 4 jj + i.
 __host__ __device__ inline int perm_row(int o) {

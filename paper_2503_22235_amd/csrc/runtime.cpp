@@ -92,6 +92,11 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     ep.H = H;
     ep.qscale = LOG2E / std::sqrt(32.0f);
     ep.perm = bf;   // bf16 W_qkv and W_1 are stored with permuted rows (perm_row)
+    if (p->rope_tab) {
+        ep.rope = p->rope_tab;
+        ep.rZ = g.Z; ep.rY = g.Y; ep.rX = g.X;
+        ep.T = T;
+    }
     WM_TIMED(PK_QKV, launch_gemm(act, w.w_qkv, M, 3 * C, C, bf, EPI_QKV, ep, s), "QKV")
 
     NatArgs na{};
@@ -174,6 +179,10 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     ep.out_amax = amax_qkv;
     ep.amax_stride = 3;
     ep.perm = 1;   // W_qkv and W_1 are stored with permuted rows (perm_row)
+    if (p->rope_tab) {
+        ep.rope = p->rope_tab;
+        ep.rZ = g.Z; ep.rY = g.Y; ep.rX = g.X;
+    }
     WM_TIMED(PK_QKV, launch_gemm_fp8(act8, w.w_qkv, M, 3 * C, C, EPI_QKV, ep, s), "QKV")
     if ((e = launch_amax_fold(amax_qkv, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
     NatArgs na{};

@@ -51,6 +51,7 @@ struct wm_processor {
     wm_precision prec = WM_F32;
     void *mem = nullptr;
     size_t bytes = 0;
+    float *rope_tab = nullptr;   // rotary (cos, sin) table, or null (no rotary embedding)
     wm::BlockWeights blk[wm::MAX_BLOCKS];
 };
 
