@@ -217,7 +217,7 @@ int wm_rollout(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
 
 /* ---- Serving: a continuous-batching forecast loop -----------------------
  * WeatherMesh-3 runs operationally, answering forecasts of any integer lead
- * time from one latent state (Sec. 2.1; Sec. 3).  A server owns a scheduler
+ * time from one latent state (Sec. 2.1; Sec. 2.2 operational encoders).  A server owns a scheduler
  * thread.  Submitted requests wait in a FIFO until a state slot in HBM is
  * free (slots are sized from the memory budget); their state is copied in
  * on a copy stream while other requests compute.  Every scheduler iteration
