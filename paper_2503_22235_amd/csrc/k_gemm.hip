@@ -40,11 +40,11 @@ __device__ __forceinline__ void epilogue4(const EpiArgs &ep, int M, int N, int m
     if (m >= M) return;
     const float4 b = *(const float4 *)(ep.bias + n);
     v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
-    if constexpr (EPI == EPI_QKV) {
+    if constexpr (epi_qkv(EPI)) {
         const int part = n / ep.C;
         const int hc = n - part * ep.C;
         const int h = hc >> 5, e = hc & 31;
-        if (ep.rope && part < 2) {
+        if (EPI == EPI_QKV_ROPE && part < 2) {
             float r[4] = {v[0], v[1], v[2], v[3]};
             rope_rotate(r, 4, e, m, ep);
             v[0] = r[0]; v[1] = r[1]; v[2] = r[2]; v[3] = r[3];
@@ -210,6 +210,7 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
     const TA *w = (const TA *)W;
     switch (epi) {
     case EPI_QKV: gemm_kernel<TA, BM, BN, EPI_QKV><<<grid, NT, 0, stream>>>(a, w, M, N, K, ep); break;
+    case EPI_QKV_ROPE: gemm_kernel<TA, BM, BN, EPI_QKV_ROPE><<<grid, NT, 0, stream>>>(a, w, M, N, K, ep); break;
     case EPI_GELU: gemm_kernel<TA, BM, BN, EPI_GELU><<<grid, NT, 0, stream>>>(a, w, M, N, K, ep); break;
     case EPI_RESID: gemm_kernel<TA, BM, BN, EPI_RESID><<<grid, NT, 0, stream>>>(a, w, M, N, K, ep); break;
     default: gemm_kernel<TA, BM, BN, EPI_STORE><<<grid, NT, 0, stream>>>(a, w, M, N, K, ep); break;

@@ -67,8 +67,8 @@ __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int
     v[0] *= dq; v[1] *= dq; v[2] *= dq; v[3] *= dq;
     const float4 b = *(const float4 *)(ep.bias + n);
     v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
-    if constexpr (EPI == EPI_QKV) {
-        if (ep.rope && n < 2 * ep.C) {
+    if constexpr (epi_qkv(EPI)) {
+        if (EPI == EPI_QKV_ROPE && n < 2 * ep.C) {
             float r[4] = {v[0], v[1], v[2], v[3]};
             rope_rotate(r, 4, hc & 31, m, ep);
             v[0] = r[0]; v[1] = r[1]; v[2] = r[2]; v[3] = r[3];
@@ -109,8 +109,8 @@ __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, in
     const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = v[i] * dq + bb[i];
-    if constexpr (EPI == EPI_QKV) {
-        if (ep.rope && n < 2 * ep.C) rope_rotate(v, 8, hc & 31, mg, ep);
+    if constexpr (epi_qkv(EPI)) {
+        if (EPI == EPI_QKV_ROPE && n < 2 * ep.C) rope_rotate(v, 8, hc & 31, mg, ep);
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] *= qs;
         store8((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * ep.Mtot + mg) * 32 + (hc & 31), v);
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         }
         const int n0 = (tn0 + t) * BN;
         // a feature tile never straddles Q/K/V (C is a multiple of BN)
-        const int part = EPI == EPI_QKV ? n0 / ep.C : 0;
+        const int part = epi_qkv(EPI) ? n0 / ep.C : 0;
         const size_t qkv_base = (size_t)part * ep.H * ep.Mtot * 32;
         const float qs = part == 0 ? ep.qscale : 1.0f;
         // per-row dequantization (fp8) and per-state amax of the outputs
@@ -351,7 +351,8 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
     constexpr int NTH = 64 * WGM * WGN;
     static bool attr_set = false;
     if (!attr_set) {
-        const void *fns[4] = {(const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8>,
+        const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8>};
@@ -384,6 +385,9 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
         switch (epi) {
         case EPI_QKV:
             gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw);
+            break;
+        case EPI_QKV_ROPE:
+            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV_ROPE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw);
             break;
         case EPI_GELU:
             gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw);

@@ -4,12 +4,12 @@
 namespace wm {
 namespace {
 
-// One wave per token row; C = 64 * VPT.  Each lane holds VPT values, read
-// as float4 (or float2) chunks interleaved across the wave so every load
-// instruction covers one contiguous span of the row.  Statistics are
-// float32 with a two-pass (mean, then centred squares) variance kept in
-// registers.
-template <int VPT, bool OBF>
+// One wave per RPW token rows; C = 64 * VPT.  Each lane holds VPT values of
+// each row, read as float4 (or float2) chunks interleaved across the wave so
+// every load instruction covers one contiguous span of a row; all rows'
+// loads are issued before any arithmetic.  Statistics are float32 with a
+// two-pass (mean, then centred squares) variance kept in registers.
+template <int VPT, bool OBF, int RPW>
 __global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict__ x,
                                                         const float *__restrict__ gamma,
                                                         const float *__restrict__ beta,
@@ -17,54 +17,62 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict_
     constexpr int C = VPT * 64;
     constexpr int W = VPT >= 4 ? 4 : VPT;     // vector width
     constexpr int NV = VPT / W;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= M) return;
+    const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
+    if (row0 >= M) return;
     const int lane = threadIdx.x & 63;
-    const float *xr = x + (size_t)row * C;
-    float v[VPT];
+    float v[RPW][VPT];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int base = (j * 64 + lane) * W;
-        if constexpr (W == 4) {
-            const float4 t = *(const float4 *)(xr + base);
-            v[4 * j] = t.x; v[4 * j + 1] = t.y; v[4 * j + 2] = t.z; v[4 * j + 3] = t.w;
-        } else {
-            const float2 t = *(const float2 *)(xr + base);
-            v[2 * j] = t.x; v[2 * j + 1] = t.y;
+    for (int r = 0; r < RPW; ++r) {
+        const float *xr = x + (size_t)min(row0 + r, M - 1) * C;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int base = (j * 64 + lane) * W;
+            if constexpr (W == 4) {
+                const float4 t = *(const float4 *)(xr + base);
+                v[r][4 * j] = t.x; v[r][4 * j + 1] = t.y; v[r][4 * j + 2] = t.z; v[r][4 * j + 3] = t.w;
+            } else {
+                const float2 t = *(const float2 *)(xr + base);
+                v[r][2 * j] = t.x; v[r][2 * j + 1] = t.y;
+            }
         }
     }
-    float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) s += v[i];
-    const float mean = wave_sum(s) * (1.0f / C);
-    float q = 0.f;
+    for (int r = 0; r < RPW; ++r) {
+        const int row = row0 + r;
+        float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-        const float d = v[i] - mean;
-        q += d * d;
-    }
-    const float var = wave_sum(q) * (1.0f / C);
-    const float rstd = 1.0f / sqrtf(var + eps);
+        for (int i = 0; i < VPT; ++i) s += v[r][i];
+        const float mean = wave_sum(s) * (1.0f / C);
+        float q = 0.f;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int base = (j * 64 + lane) * W;
-        float y[W];
+        for (int i = 0; i < VPT; ++i) {
+            const float d = v[r][i] - mean;
+            q += d * d;
+        }
+        const float var = wave_sum(q) * (1.0f / C);
+        const float rstd = 1.0f / sqrtf(var + eps);
+        if (row >= M) continue;
 #pragma unroll
-        for (int t = 0; t < W; ++t) y[t] = (v[W * j + t] - mean) * rstd * gamma[base + t] + beta[base + t];
-        if constexpr (OBF) {
-            bf16 *o = (bf16 *)out + (size_t)row * C + base;
-            if constexpr (W == 4) {
-                uint2 u;
-                u.x = (unsigned)f2bf_bits(y[0]) | ((unsigned)f2bf_bits(y[1]) << 16);
-                u.y = (unsigned)f2bf_bits(y[2]) | ((unsigned)f2bf_bits(y[3]) << 16);
-                *(uint2 *)o = u;
+        for (int j = 0; j < NV; ++j) {
+            const int base = (j * 64 + lane) * W;
+            float y[W];
+#pragma unroll
+            for (int t = 0; t < W; ++t) y[t] = (v[r][W * j + t] - mean) * rstd * gamma[base + t] + beta[base + t];
+            if constexpr (OBF) {
+                bf16 *o = (bf16 *)out + (size_t)row * C + base;
+                if constexpr (W == 4) {
+                    uint2 u;
+                    u.x = (unsigned)f2bf_bits(y[0]) | ((unsigned)f2bf_bits(y[1]) << 16);
+                    u.y = (unsigned)f2bf_bits(y[2]) | ((unsigned)f2bf_bits(y[3]) << 16);
+                    *(uint2 *)o = u;
+                } else {
+                    *(unsigned *)o = (unsigned)f2bf_bits(y[0]) | ((unsigned)f2bf_bits(y[1]) << 16);
+                }
             } else {
-                *(unsigned *)o = (unsigned)f2bf_bits(y[0]) | ((unsigned)f2bf_bits(y[1]) << 16);
+                float *o = (float *)out + (size_t)row * C + base;
+                if constexpr (W == 4) *(float4 *)o = make_float4(y[0], y[1], y[2], y[3]);
+                else *(float2 *)o = make_float2(y[0], y[1]);
             }
-        } else {
-            float *o = (float *)out + (size_t)row * C + base;
-            if constexpr (W == 4) *(float4 *)o = make_float4(y[0], y[1], y[2], y[3]);
-            else *(float2 *)o = make_float2(y[0], y[1]);
         }
     }
 }
@@ -72,9 +80,10 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict_
 template <int VPT>
 hipError_t ln_launch(const float *x, const float *g, const float *b, void *out, bool obf, int M, float eps,
                      hipStream_t s) {
-    const int grid = (M + 3) / 4;
-    if (obf) layernorm_kernel<VPT, true><<<grid, 256, 0, s>>>(x, g, b, out, M, eps);
-    else layernorm_kernel<VPT, false><<<grid, 256, 0, s>>>(x, g, b, out, M, eps);
+    constexpr int RPW = 2;
+    const int grid = (M + 4 * RPW - 1) / (4 * RPW);
+    if (obf) layernorm_kernel<VPT, true, RPW><<<grid, 256, 0, s>>>(x, g, b, out, M, eps);
+    else layernorm_kernel<VPT, false, RPW><<<grid, 256, 0, s>>>(x, g, b, out, M, eps);
     return hipGetLastError();
 }
 

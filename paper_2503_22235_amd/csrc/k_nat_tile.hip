@@ -264,11 +264,12 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
     }
 
     f32x4 oacc[2][2], lacc[2];
-    float mref[2];
+    float mref[2], thr[2];          // reference maxima and the level that moves them
 #pragma unroll
     for (int G = 0; G < 2; ++G) {
         oacc[G][0] = oacc[G][1] = lacc[G] = f32x4{0.f, 0.f, 0.f, 0.f};
         mref[G] = -1e30f;
+        thr[G] = -1e30f;
     }
     bf16x8 ones;
 #pragma unroll
@@ -331,12 +332,13 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
             // Move the reference maxima only when some lane's scores exceed
             // them by TAU; the new maximum is taken over the 4 lanes that
             // share each query, so all of them keep the same reference.
-            if (__builtin_amdgcn_ballot_w64(cm[0] > mref[0] + TAU || cm[1] > mref[1] + TAU)) {
+            if (__builtin_amdgcn_ballot_w64(cm[0] > thr[0] || cm[1] > thr[1])) {
 #pragma unroll
                 for (int G = 0; G < 2; ++G) {
                     const float mn = fmaxf(mref[G], xmax16_32(cm[G]));
                     const float al = __builtin_amdgcn_exp2f(mref[G] - mn);
                     mref[G] = mn;
+                    thr[G] = mn + TAU;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         oacc[G][0][i] *= al;

@@ -20,8 +20,10 @@ enum EpiKind : int {
     EPI_QKV = 0,    // +bias; Q columns * qscale; scatter to head-major [3][H][M][32]
     EPI_GELU = 1,   // gelu(+bias) -> out [M][N]
     EPI_RESID = 2,  // resid[m][n] += acc + bias (float32 in place)
-    EPI_STORE = 3   // +bias -> out [M][N]
+    EPI_STORE = 3,  // +bias -> out [M][N]
+    EPI_QKV_ROPE = 4  // EPI_QKV with q and k rotated (EpiArgs.rope)
 };
+constexpr bool epi_qkv(int e) { return e == EPI_QKV || e == EPI_QKV_ROPE; }
 struct EpiArgs {
     const float *bias;  // [N]
     void *out;          // EPI_QKV / EPI_GELU / EPI_STORE output

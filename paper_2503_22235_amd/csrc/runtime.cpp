@@ -97,7 +97,7 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
         ep.rZ = g.Z; ep.rY = g.Y; ep.rX = g.X;
         ep.T = T;
     }
-    WM_TIMED(PK_QKV, launch_gemm(act, w.w_qkv, M, 3 * C, C, bf, EPI_QKV, ep, s), "QKV")
+    WM_TIMED(PK_QKV, launch_gemm(act, w.w_qkv, M, 3 * C, C, bf, p->rope_tab ? EPI_QKV_ROPE : EPI_QKV, ep, s), "QKV")
 
     NatArgs na{};
     const size_t plane = (size_t)H * M * 32 * esz;
@@ -183,7 +183,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
         ep.rope = p->rope_tab;
         ep.rZ = g.Z; ep.rY = g.Y; ep.rX = g.X;
     }
-    WM_TIMED(PK_QKV, launch_gemm_fp8(act8, w.w_qkv, M, 3 * C, C, EPI_QKV, ep, s), "QKV")
+    WM_TIMED(PK_QKV, launch_gemm_fp8(act8, w.w_qkv, M, 3 * C, C, p->rope_tab ? EPI_QKV_ROPE : EPI_QKV, ep, s), "QKV")
     if ((e = launch_amax_fold(amax_qkv, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
     NatArgs na{};
     const size_t plane = (size_t)H * M * 32 * 2;
