@@ -103,14 +103,22 @@ __device__ __forceinline__ void store8(bf16 *p, const float *v) {
 // the float32 residual).  Same conventions as epilogue4.
 template <int EPI>
 __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, int n, f32x4 a, f32x4 c,
-                                           size_t qkv_base, int hc, float qs, float dq) {
+                                           size_t qkv_base, int hc, float qs, float dq, const float2 *rc) {
     float v[8] = {a[0], a[1], a[2], a[3], c[0], c[1], c[2], c[3]};
     const float4 b0 = *(const float4 *)(ep.bias + n), b1 = *(const float4 *)(ep.bias + n + 4);
     const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = v[i] * dq + bb[i];
     if constexpr (epi_qkv(EPI)) {
-        if (EPI == EPI_QKV_ROPE && n < 2 * ep.C) rope_rotate(v, 8, hc & 31, mg, ep);
+        if (EPI == EPI_QKV_ROPE && n < 2 * ep.C) {
+            // rc: (cos, sin) of this row's 4 channel pairs (hc & 31) / 2 ..
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float a0 = v[2 * i], a1 = v[2 * i + 1];
+                v[2 * i] = a0 * rc[i].x - a1 * rc[i].y;
+                v[2 * i + 1] = a0 * rc[i].y + a1 * rc[i].x;
+            }
+        }
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] *= qs;
         store8((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * ep.Mtot + mg) * 32 + (hc & 31), v);
@@ -299,6 +307,27 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
             dq[i] = FP8 ? ep.a_amax[srow[i]] * (1.0f / 448.0f) * ep.w_dequant : 1.0f;
         }
         const int s_lo = ep.out_amax ? (int)(((long)min(m0, M - 1) + ep.row0) / ep.T) : 0;
+        // rotary (cos, sin) of each row's channel pairs 4g .. 4g+3 (the same
+        // pairs in every head this lane stores), loaded once per tile
+        float2 rc[TM][4];
+        if constexpr (EPI == EPI_QKV_ROPE) {
+            if (ep.perm && part < 2) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const long mg = (long)min(m0 + wm * WM + 16 * i + r16, M - 1) + ep.row0;
+                    const unsigned tt = (unsigned)(mg % ep.T);
+                    const unsigned yx = (unsigned)(ep.rY * ep.rX);
+                    const int z = (int)(tt / yx), y = (int)((tt / (unsigned)ep.rX) % (unsigned)ep.rY),
+                              x = (int)(tt % (unsigned)ep.rX);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int pr = 4 * g + q;
+                        const int row = pr < 4 ? z : (pr < 10 ? ep.rZ + y : ep.rZ + ep.rY + x);
+                        rc[i][q] = *(const float2 *)(ep.rope + 2 * (row * 16 + pr));
+                    }
+                }
+            }
+        }
         float mlo = 0.f, mhi = 0.f;
 #pragma unroll
         for (int j = 0; j < TN; j += 2)
@@ -311,7 +340,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
                     if (ep.perm) {
                         const int n = n0 + wn * WN + 16 * j + 8 * g;
                         a = epilogue8<EPI>(ep, N, mg, n, acc[j][i], acc[j + 1][i], qkv_base, n - part * ep.C, qs,
-                                           dq[i]);
+                                           dq[i], rc[i]);
                     } else {
                         const int n = n0 + wn * WN + 16 * j + 4 * g;
                         a = fmaxf(epilogue4<EPI>(ep, N, mg, n, acc[j][i], qkv_base, n - part * ep.C, qs, dq[i]),
