@@ -154,8 +154,8 @@ int wm_quantize_fp8(size_t n, const float *x, float mul, unsigned char *out,
 /* One linear map on e4m3 operands with float32 accumulation:
  *   r[m][n] = a_dequant * w_dequant * sum_k a8[m][k] * w8[n][k] + bias[n]
  * a8 [M][K], w8 [N][K] device e4m3 codes; epilogue and out as wm_linear
- * (0 and 1 write bfloat16).  N % 128 == 0, K % 128 == 0.  Waits for the
- * stream before returning (it owns a temporary device scale). */
+ * (0 and 1 write bfloat16).  N % 128 == 0, K % 128 == 0.  Enqueued on
+ * `stream`; allocates nothing. */
 int wm_linear_fp8(int M, int N, int K, const void *a8, float a_dequant,
                   const void *w8, float w_dequant, const float *bias,
                   int epilogue, void *out, void *stream);

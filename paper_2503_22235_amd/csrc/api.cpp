@@ -253,30 +253,18 @@ int wm_linear_fp8(int M, int N, int K, const void *a8, float a_dequant, const vo
     if (epilogue < 0 || epilogue > 2) return fail(WM_EINVAL, "epilogue must be 0, 1 or 2");
     if (M == 0) return WM_OK;
     if (!a8 || !w8 || !bias || !out) return fail(WM_EINVAL, "NULL tensor");
-    // one state holding all M rows; its amax is a_dequant * 448
-    float *amax_dev = nullptr;
-    hipError_t e = hipMalloc(&amax_dev, sizeof(float));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
-    const float amax = a_dequant * 448.0f;
     hipStream_t s = (hipStream_t)stream;
-    if ((e = hipMemcpyAsync(amax_dev, &amax, sizeof amax, hipMemcpyHostToDevice, s)) != hipSuccess) {
-        (void)hipFree(amax_dev);
-        return hip_fail(e, "copy");
-    }
     EpiArgs ep{};
     ep.bias = bias;
-    ep.a_amax = amax_dev;
+    ep.a_dequant = a_dequant;     // one scale for all rows
     ep.w_dequant = w_dequant;
     ep.T = M;
     EpiKind kind = EPI_STORE;
     if (epilogue == 1) { kind = EPI_GELU; ep.out = out; }
     else if (epilogue == 2) { kind = EPI_RESID; ep.resid = (float *)out; }
     else ep.out = out;
-    e = launch_gemm_fp8(a8, w8, M, N, K, kind, ep, s);
-    const hipError_t e2 = hipStreamSynchronize(s);
-    (void)hipFree(amax_dev);
-    if (e != hipSuccess) return hip_fail(e, "gemm launch");
-    return e2 == hipSuccess ? WM_OK : hip_fail(e2, "sync");
+    const hipError_t e = launch_gemm_fp8(a8, w8, M, N, K, kind, ep, s);
+    return e == hipSuccess ? WM_OK : hip_fail(e, "gemm launch");
 }
 
 int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_ratio, wm_precision prec,

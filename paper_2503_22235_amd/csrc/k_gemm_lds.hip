@@ -304,7 +304,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         for (int i = 0; i < TM; ++i) {
             const long mg = (long)min(m0 + wm * WM + 16 * i + r16, M - 1) + ep.row0;
             srow[i] = FP8 || ep.out_amax ? (int)(mg / ep.T) : 0;
-            dq[i] = FP8 ? ep.a_amax[srow[i]] * (1.0f / 448.0f) * ep.w_dequant : 1.0f;
+            dq[i] = FP8 ? (ep.a_amax ? ep.a_amax[srow[i]] * (1.0f / 448.0f) : ep.a_dequant) * ep.w_dequant : 1.0f;
         }
         const int s_lo = ep.out_amax ? (int)(((long)min(m0, M - 1) + ep.row0) / ep.T) : 0;
         // rotary (cos, sin) of each row's channel pairs 4g .. 4g+3 (the same

@@ -30,8 +30,10 @@ struct EpiArgs {
     float *resid;       // EPI_RESID target
     int C, H;           // EPI_QKV: model width and heads (d = 32)
     float qscale;       // EPI_QKV: factor on Q columns
-    // FP8 operands: acc * (a_amax[state of row] / 448) * w_dequant
+    // FP8 operands: acc * (a_amax[state of row] / 448) * w_dequant, or
+    // acc * a_dequant * w_dequant when a_amax is null (one scale for all rows)
     const float *a_amax;
+    float a_dequant;
     float w_dequant;
     long T;             // tokens per state
     // optional: per-state amax of the stored outputs (float bits), index
