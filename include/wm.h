@@ -55,7 +55,7 @@ typedef enum {
  * their axis.  periodic_mask: bit0 = Z, bit1 = Y, bit2 = X; the paper's
  * setting is 0x4 -- longitude wraps around the sphere (its own circular
  * padding), latitude and level windows keep their size and shift inward at
- * the borders (NATTEN's border behaviour, "bump attention") (App. A.2). */
+ * the borders (NATTEN's border behaviour) (App. A.2). */
 typedef struct {
     int Z, Y, X;
     int C, heads;

@@ -12,7 +12,7 @@
  *     periodic axis (lon, circular padding):  key_t = (i - r + t) mod N,
  *                                             offset = t - r
  *     clamped axis (lat and level, the window keeps its size and slides
- *     inward at the border, "bump attention"):
+ *     inward at the border, NATTEN's border behaviour):
  *                                             start = min(max(i-r, 0), N-K)
  *                                             key_t = start + t,
  *                                             offset = key_t - i

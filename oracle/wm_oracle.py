@@ -17,7 +17,7 @@ What is computed (section references are to the WeatherMesh-3 paper):
   latent token attends to the Kz x Ky x Kx box of tokens around it over
   (level, lat, lon).  Longitude wraps (the paper's own circular padding,
   App. A.2); latitude uses NATTEN's border behaviour, where the window keeps
-  its full size and shifts inward at the poles ("bump attention", App. A.2);
+  its full size and shifts inward at the poles (NATTEN's border behaviour, App. A.2);
   the level axis is treated like latitude.
 * Relative-position bias: a learned per-head table indexed by the key minus
   query offset on each axis.  The paper itself encodes position with rotary
