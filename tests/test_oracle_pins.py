@@ -462,3 +462,19 @@ def test_block_rope_wiring_and_lon_roll():
     assert np.abs(yr - np.roll(y, 3, axis=2)).max() < 1e-10
     # and differs from the block without rotation
     assert np.abs(y - O.block(x, p, g, rope=False)).max() > 1e-6
+
+
+def test_e4m3_codec_matches_torch_float8():
+    """Inside the finite range (|x| <= 448) the oracle's e4m3 round trip is
+    torch's float8_e4m3fn conversion (an independent implementation of the
+    OCP format with round to nearest even); outside it the oracle saturates
+    where torch gives NaN."""
+    import torch
+    r = np.random.default_rng(0)
+    x = np.concatenate([np.linspace(-448.0, 448.0, 200001), r.standard_normal(100000) * 10.0,
+                        [0.0, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -10, 1.0625, 1.0625 + 1e-6]]).astype(np.float32)
+    x = x[np.abs(x) <= 448.0]
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    got = O.e4m3_decode(O.e4m3_encode(x))
+    assert np.array_equal(got, ref)
+    assert O.e4m3_decode(O.e4m3_encode(np.float32([500.0, -1e6])))[0] == 448.0
