@@ -299,6 +299,8 @@ def main():
     ap.add_argument("--no-fp8", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-hourly", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the rotary, ensemble, C=1024 and hourly-forecast lines")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run a plain copy of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -387,37 +389,40 @@ def main():
     if args.copy_probe_mib:
         copy_probe(torch, args.copy_probe_mib)
 
+    if args.no_extras:
+        args.no_hourly = True
     # ---- the same processor with rotary q/k (the paper's position encoding)
-    wm.wm_processor_set_rope(p_bf, True)
-    x.copy_(torch.from_numpy(x0[:1].copy()))
-    dtr, _ = time_steps(wm, torch, ctx, p_bf, x, 1, args.steps, 1)
-    out["bf16_rope"] = {"steps_per_s": round(args.steps / dtr, 3), "ms_per_step": round(dtr / args.steps * 1e3, 3)}
-    wm.wm_processor_set_rope(p_bf, False)
+    if not args.no_extras:
+        wm.wm_processor_set_rope(p_bf, True)
+        x.copy_(torch.from_numpy(x0[:1].copy()))
+        dtr, _ = time_steps(wm, torch, ctx, p_bf, x, 1, args.steps, 1)
+        out["bf16_rope"] = {"steps_per_s": round(args.steps / dtr, 3), "ms_per_step": round(dtr / args.steps * 1e3, 3)}
+        wm.wm_processor_set_rope(p_bf, False)
 
-    # ---- an ensemble of 8 states through batched launches
-    x8 = torch.from_numpy(x0[:1].copy()).cuda().repeat(8, 1, 1, 1, 1)
-    k8b = max(2, args.steps // 4)
-    dte, _ = time_steps(wm, torch, ctx, p_bf, x8, 8, k8b, 1)
-    out["bf16_ensemble_b8"] = {"state_steps_per_s": round(8 * k8b / dte, 3), "ms_per_batch_step": round(dte / k8b * 1e3, 2)}
-    del x8
+        # ---- an ensemble of 8 states through batched launches
+        x8 = torch.from_numpy(x0[:1].copy()).cuda().repeat(8, 1, 1, 1, 1)
+        k8b = max(2, args.steps // 4)
+        dte, _ = time_steps(wm, torch, ctx, p_bf, x8, 8, k8b, 1)
+        out["bf16_ensemble_b8"] = {"state_steps_per_s": round(8 * k8b / dte, 3), "ms_per_batch_step": round(dte / k8b * 1e3, 2)}
+        del x8
 
-    # ---- one block at the encoder/decoder width (C=1024, 32 heads)
-    gw = S.Grid(Z=8, Y=90, X=180, C=1024, heads=32, Kz=5, Ky=7, Kx=7, periodic_mask=4)
-    pw = wm.wm_processor_create(ctx, gw, 1, 4, wm.WM_BF16, S.processor_params(gw, 1, seed=1))
-    xw = torch.from_numpy(S.latent_state(gw, 1, seed=0)).cuda()
-    for _ in range(2):
-        wm.wm_processor_block(ctx, pw, 0, 1, xw)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(5):
-        wm.wm_processor_block(ctx, pw, 0, 1, xw)
-    torch.cuda.synchronize()
-    dtw = (time.perf_counter() - t0) / 5
-    fw = gw.T * (2 * (3 + 1 + 8) * gw.C * gw.C + 4 * gw.C * 245)
-    out["width_1024_block"] = {"ms": round(dtw * 1e3, 3), "tflops": round(fw / dtw / 1e12, 1),
-                               "mfma_frac": round(fw / dtw / (PEAK_BF16_TFLOPS * 1e12), 4)}
-    pw.close()
-    del xw
+        # ---- one block at the encoder/decoder width (C=1024, 32 heads)
+        gw = S.Grid(Z=8, Y=90, X=180, C=1024, heads=32, Kz=5, Ky=7, Kx=7, periodic_mask=4)
+        pw = wm.wm_processor_create(ctx, gw, 1, 4, wm.WM_BF16, S.processor_params(gw, 1, seed=1))
+        xw = torch.from_numpy(S.latent_state(gw, 1, seed=0)).cuda()
+        for _ in range(2):
+            wm.wm_processor_block(ctx, pw, 0, 1, xw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            wm.wm_processor_block(ctx, pw, 0, 1, xw)
+        torch.cuda.synchronize()
+        dtw = (time.perf_counter() - t0) / 5
+        fw = gw.T * (2 * (3 + 1 + 8) * gw.C * gw.C + 4 * gw.C * 245)
+        out["width_1024_block"] = {"ms": round(dtw * 1e3, 3), "tflops": round(fw / dtw / 1e12, 1),
+                                   "mfma_frac": round(fw / dtw / (PEAK_BF16_TFLOPS * 1e12), 4)}
+        pw.close()
+        del xw
 
     # ---- hourly 14-day forecast (prefix sharing: 56 six-hour + 280 one-hour steps)
     p1_bf = wm.wm_processor_create(ctx, g, nb, 4, wm.WM_BF16, S.processor_params(g, nb, seed=2, proc=1))
