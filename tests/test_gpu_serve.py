@@ -100,3 +100,59 @@ def test_serve_result_against_oracle(env):
     srv.close()
     p6.close()
     p1.close()
+
+
+def test_serve_host_forced_limits(env):
+    """Limits forced from the host: a budget below one slot, a two-slot budget
+    that makes requests wait, unknown ids and invalid configurations."""
+    wm, torch, ctx, g, p6p, p1p = env
+    p6 = wm.wm_processor_create(ctx, g, 2, 4, 0, p6p)
+    p1 = wm.wm_processor_create(ctx, g, 2, 4, 0, p1p)
+    shape = (g.Z, g.Y, g.X, g.C)
+    slot_bytes = (g.Z * g.Y * g.X * g.C * 4 + 255) // 256 * 256
+    say("serve limits: slot", slot_bytes, "bytes")
+    # a budget that holds no slot is refused at creation
+    with pytest.raises(wm.WmError) as ei:
+        wm.wm_serve_create(ctx, p6, p1, max_batch=2, state_bf16=False, hbm_budget_bytes=slot_bytes - 1)
+    assert ei.value.code == -2
+    # invalid configurations
+    for kw in (dict(max_batch=0), dict(max_batch=65), dict(max_slots=-1), dict(max_slots=1025)):
+        with pytest.raises(wm.WmError) as ei:
+            wm.wm_serve_create(ctx, p6, p1, state_bf16=False, **kw)
+        assert ei.value.code == -1, kw
+    g2 = S.Grid(Z=4, Y=9, X=16, C=128, heads=4, Kz=3, Ky=3, Kx=5)
+    q1 = wm.wm_processor_create(ctx, g2, 2, 4, 0, S.processor_params(g2, 2, seed=2, proc=1))
+    with pytest.raises(wm.WmError) as ei:
+        wm.wm_serve_create(ctx, p6, q1, state_bf16=False)
+    assert ei.value.code == -1
+    q1.close()
+    # a budget of exactly two slots: requests wait for a slot, results do not change
+    srv = wm.wm_serve_create(ctx, p6, p1, max_batch=4, state_bf16=False, hbm_budget_bytes=2 * slot_bytes)
+    assert wm.wm_serve_status(srv)["slots"] == 2
+    leads = [12, 7, 0, 13, 6, 1, 18, 5]
+    states = S.latent_state(g, len(leads), seed=9)
+    ids = [wm.wm_serve_submit(srv, states[i], leads[i]) for i in range(len(leads))]
+    with pytest.raises(wm.WmError) as ei:
+        wm.wm_serve_submit(srv, states[0], -1)
+    assert ei.value.code == -1
+    with pytest.raises(wm.WmError) as ei:
+        wm.wm_serve_poll(srv, max(ids) + 1000)
+    assert ei.value.code == -5
+    res, st = drain(wm, srv, ids, shape)
+    srv.close()
+    # slot occupancy: a slot is held from before t_admit until t_done
+    events = sorted([(st[r]["t_admit"], 1) for r in ids] + [(st[r]["t_done"], -1) for r in ids],
+                    key=lambda e: (e[0], e[1]))
+    held = peak = 0
+    for _, d in events:
+        held += d
+        peak = max(peak, held)
+    say("serve limits: peak slots held", peak)
+    assert peak <= 2
+    for i, rid in enumerate(ids):
+        xd = torch.from_numpy(states[i:i + 1].copy()).cuda()
+        wm.wm_rollout(ctx, p6, p1, 1, xd, leads[i])
+        assert np.array_equal(xd.cpu().numpy()[0], res[rid]), f"request {i} (lead {leads[i]})"
+        assert st[rid]["steps"] == len(O.schedule(leads[i]))
+    p6.close()
+    p1.close()
