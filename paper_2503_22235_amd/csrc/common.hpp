@@ -17,13 +17,16 @@ typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 constexpr int WAVE = 64;
 constexpr float LOG2E = 1.4426950408889634f;
 
-// float32 -> bfloat16 bits, round to nearest even (NaN kept quiet).
+// float32 -> bfloat16 bits, round to nearest even (NaN kept quiet): the
+// gfx950 conversion instruction (v_cvt_pk_bf16_f32) does exactly this.
 __device__ __forceinline__ unsigned short f2bf_bits(float f) {
-    unsigned int u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
-        return (unsigned short)((u >> 16) | 0x0040u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    return __builtin_bit_cast(unsigned short, (bf16)f);
+}
+// Two floats -> packed bfloat16 pair (lo in bits 0..15), one instruction.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned pack_bf16x2(float lo, float hi) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
 }
 __device__ __forceinline__ float bf_bits2f(unsigned short b) {
     return __uint_as_float(((unsigned int)b) << 16);

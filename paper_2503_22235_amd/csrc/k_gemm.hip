@@ -29,8 +29,8 @@ __device__ __forceinline__ void store4(float *p, f32x4 v) {
 }
 __device__ __forceinline__ void store4(bf16 *p, f32x4 v) {
     uint2 u;
-    u.x = (unsigned)f2bf_bits(v[0]) | ((unsigned)f2bf_bits(v[1]) << 16);
-    u.y = (unsigned)f2bf_bits(v[2]) | ((unsigned)f2bf_bits(v[3]) << 16);
+    u.x = pack_bf16x2(v[0], v[1]);
+    u.y = pack_bf16x2(v[2], v[3]);
     *(uint2 *)p = u;
 }
 

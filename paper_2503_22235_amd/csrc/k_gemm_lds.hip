@@ -52,8 +52,8 @@ __device__ __forceinline__ void store4(float *p, f32x4 v) {
 }
 __device__ __forceinline__ void store4(bf16 *p, f32x4 v) {
     uint2 u;
-    u.x = (unsigned)f2bf_bits(v[0]) | ((unsigned)f2bf_bits(v[1]) << 16);
-    u.y = (unsigned)f2bf_bits(v[2]) | ((unsigned)f2bf_bits(v[3]) << 16);
+    u.x = pack_bf16x2(v[0], v[1]);
+    u.y = pack_bf16x2(v[2], v[3]);
     *(uint2 *)p = u;
 }
 
@@ -91,10 +91,10 @@ __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int
 
 __device__ __forceinline__ void store8(bf16 *p, const float *v) {
     uint4 u;
-    u.x = (unsigned)f2bf_bits(v[0]) | ((unsigned)f2bf_bits(v[1]) << 16);
-    u.y = (unsigned)f2bf_bits(v[2]) | ((unsigned)f2bf_bits(v[3]) << 16);
-    u.z = (unsigned)f2bf_bits(v[4]) | ((unsigned)f2bf_bits(v[5]) << 16);
-    u.w = (unsigned)f2bf_bits(v[6]) | ((unsigned)f2bf_bits(v[7]) << 16);
+    u.x = pack_bf16x2(v[0], v[1]);
+    u.y = pack_bf16x2(v[2], v[3]);
+    u.z = pack_bf16x2(v[4], v[5]);
+    u.w = pack_bf16x2(v[6], v[7]);
     *(uint4 *)p = u;
 }
 

@@ -62,11 +62,11 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict_
                 bf16 *o = (bf16 *)out + (size_t)row * C + base;
                 if constexpr (W == 4) {
                     uint2 u;
-                    u.x = (unsigned)f2bf_bits(y[0]) | ((unsigned)f2bf_bits(y[1]) << 16);
-                    u.y = (unsigned)f2bf_bits(y[2]) | ((unsigned)f2bf_bits(y[3]) << 16);
+                    u.x = pack_bf16x2(y[0], y[1]);
+                    u.y = pack_bf16x2(y[2], y[3]);
                     *(uint2 *)o = u;
                 } else {
-                    *(unsigned *)o = (unsigned)f2bf_bits(y[0]) | ((unsigned)f2bf_bits(y[1]) << 16);
+                    *(unsigned *)o = pack_bf16x2(y[0], y[1]);
                 }
             } else {
                 float *o = (float *)out + (size_t)row * C + base;

@@ -382,8 +382,8 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         for (int tt = 0; tt < 2; ++tt) {
             f32x4 v = oacc[G][tt];
             uint2 u;
-            u.x = (unsigned)f2bf_bits(v[0] * inv) | ((unsigned)f2bf_bits(v[1] * inv) << 16);
-            u.y = (unsigned)f2bf_bits(v[2] * inv) | ((unsigned)f2bf_bits(v[3] * inv) << 16);
+            u.x = pack_bf16x2(v[0] * inv, v[1] * inv);
+            u.y = pack_bf16x2(v[2] * inv, v[3] * inv);
             *(uint2 *)(ob + 16 * tt + 4 * g) = u;
         }
     }
@@ -736,8 +736,8 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
         for (int tt = 0; tt < 2; ++tt) {
             f32x4 v = oacc[G][tt];
             uint2 u;
-            u.x = (unsigned)f2bf_bits(v[0] * inv) | ((unsigned)f2bf_bits(v[1] * inv) << 16);
-            u.y = (unsigned)f2bf_bits(v[2] * inv) | ((unsigned)f2bf_bits(v[3] * inv) << 16);
+            u.x = pack_bf16x2(v[0] * inv, v[1] * inv);
+            u.y = pack_bf16x2(v[2] * inv, v[3] * inv);
             *(uint2 *)(ob + 16 * tt + 4 * g) = u;
         }
     }
