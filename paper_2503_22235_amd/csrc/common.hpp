@@ -65,20 +65,22 @@ __device__ __forceinline__ float wave_max(float v) {
 // GELU(z) = z * Phi(z) = z/2 * (1 + erf(z / sqrt 2)), with erf from the
 // rational approximation of Abramowitz & Stegun, Handbook of Mathematical
 // Functions, eq. 7.1.26 (Hastings): for x >= 0,
-//   erf(x) = 1 - (a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5) exp(-x^2),
+//   erf(x) = 1 - P(t) exp(-x^2),  P(t) = a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5,
 //   t = 1 / (1 + p x),  |error| <= 1.5e-7.
+// With x = |z| / sqrt 2 and erf odd, both signs of z collapse to
+//   GELU(z) = max(z, 0) - |z|/2 * P(t) * exp(-z^2 / 2),
+// which needs no sign select; the 1/2 and 1/sqrt 2 are folded into the
+// constants.
 __device__ __forceinline__ float gelu_as(float z) {
-    const float x = fabsf(z) * 0.70710678118654752f;
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-    float poly = fmaf(1.061405429f, t, -1.453152027f);
-    poly = fmaf(poly, t, 1.421413741f);
-    poly = fmaf(poly, t, -0.284496736f);
-    poly = fmaf(poly, t, 0.254829592f);
-    poly *= t;
-    const float ex = __builtin_amdgcn_exp2f(-x * x * LOG2E);
-    float erfx = fmaf(-poly, ex, 1.0f);
-    erfx = z < 0.f ? -erfx : erfx;
-    return 0.5f * z * (1.0f + erfx);
+    const float az = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
+    float q = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
+    q = fmaf(q, t, 0.5f * 1.421413741f);
+    q = fmaf(q, t, 0.5f * -0.284496736f);
+    q = fmaf(q, t, 0.5f * 0.254829592f);
+    const float s = q * t * az;
+    const float ex = __builtin_amdgcn_exp2f(z * z * (-0.5f * LOG2E));
+    return fmaf(-s, ex, fmaxf(z, 0.0f));
 }
 
 // ---------------------------------------------------------------------------

@@ -86,6 +86,7 @@ __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int
     } else {
         store4((bf16 *)ep.out + (size_t)m * N + n, v);
     }
+    if (!ep.out_amax) return 0.f;           // amax only feeds FP8 requantization
     return fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3])));
 }
 
@@ -136,6 +137,7 @@ __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, in
     } else {
         store8((bf16 *)ep.out + (size_t)mg * N + n, v);
     }
+    if (!ep.out_amax) return 0.f;
     float m = 0.f;
 #pragma unroll
     for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
