@@ -50,6 +50,14 @@ template <> struct Elt<bf16> {
     static __device__ __forceinline__ void st(bf16 *p, float v) { *p = f2bf(v); }
 };
 
+// Maximum of floats as one gfx950 v_maximum3_f32 / v_maximum_f32: unlike
+// fmaxf it needs no NaN-quieting pass over its operands (a NaN operand
+// propagates instead of being dropped).
+__device__ __forceinline__ float max2f(float a, float b) { return __builtin_elementwise_maximum(a, b); }
+__device__ __forceinline__ float max3f(float a, float b, float c) {
+    return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
+}
+
 // Wave-wide reductions (64 lanes).
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll

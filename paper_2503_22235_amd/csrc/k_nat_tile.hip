@@ -63,9 +63,9 @@ __device__ __forceinline__ void *uniform_ptr(const void *p) {
 
 __device__ __forceinline__ float xmax16_32(float v) {
     auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+    v = max2f(__uint_as_float(a[0]), __uint_as_float(a[1]));
     auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+    return max2f(__uint_as_float(b[0]), __uint_as_float(b[1]));
 }
 
 // QSCALED: q already carries the factor log2(e)/sqrt(d) (the block path folds
@@ -327,15 +327,15 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
                 }
 #pragma unroll
             for (int G = 0; G < 2; ++G)
-                cm[G] = fmaxf(fmaxf(fmaxf(s[G][0][0], s[G][0][1]), fmaxf(s[G][0][2], s[G][0][3])),
-                              fmaxf(fmaxf(s[G][1][0], s[G][1][1]), fmaxf(s[G][1][2], s[G][1][3])));
+                cm[G] = max3f(max3f(s[G][0][0], s[G][0][1], s[G][0][2]), max3f(s[G][0][3], s[G][1][0], s[G][1][1]),
+                              max2f(s[G][1][2], s[G][1][3]));
             // Move the reference maxima only when some lane's scores exceed
             // them by TAU; the new maximum is taken over the 4 lanes that
             // share each query, so all of them keep the same reference.
             if (__builtin_amdgcn_ballot_w64(cm[0] > thr[0] || cm[1] > thr[1])) {
 #pragma unroll
                 for (int G = 0; G < 2; ++G) {
-                    const float mn = fmaxf(mref[G], xmax16_32(cm[G]));
+                    const float mn = max2f(mref[G], xmax16_32(cm[G]));
                     const float al = __builtin_amdgcn_exp2f(mref[G] - mn);
                     mref[G] = mn;
                     thr[G] = mn + TAU;
@@ -675,12 +675,12 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
                 }
 #pragma unroll
             for (int G = 0; G < 2; ++G)
-                cm[G] = fmaxf(fmaxf(fmaxf(s[G][0][0], s[G][0][1]), fmaxf(s[G][0][2], s[G][0][3])),
-                              fmaxf(fmaxf(s[G][1][0], s[G][1][1]), fmaxf(s[G][1][2], s[G][1][3])));
+                cm[G] = max3f(max3f(s[G][0][0], s[G][0][1], s[G][0][2]), max3f(s[G][0][3], s[G][1][0], s[G][1][1]),
+                              max2f(s[G][1][2], s[G][1][3]));
             if (__builtin_amdgcn_ballot_w64(cm[0] > thr[0] || cm[1] > thr[1])) {
 #pragma unroll
                 for (int G = 0; G < 2; ++G) {
-                    const float mn = fmaxf(mref[G], xmax16_32(cm[G]));
+                    const float mn = max2f(mref[G], xmax16_32(cm[G]));
                     const float al = __builtin_amdgcn_exp2f(c * (mref[G] - mn));
                     mref[G] = mn;
                     thr[G] = mn + tau_raw;
