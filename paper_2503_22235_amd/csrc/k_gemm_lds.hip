@@ -63,9 +63,8 @@ __device__ __forceinline__ void store4(bf16 *p, f32x4 v) {
 // (1 for K and V): all but hc are uniform over the tile.
 template <int EPI>
 __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int n, f32x4 v,
-                                           size_t qkv_base, int hc, float qs, float dq) {
+                                           size_t qkv_base, int hc, float qs, float dq, float4 b, float4 rr) {
     v[0] *= dq; v[1] *= dq; v[2] *= dq; v[3] *= dq;
-    const float4 b = *(const float4 *)(ep.bias + n);
     v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
     if constexpr (epi_qkv(EPI)) {
         if (EPI == EPI_QKV_ROPE && n < 2 * ep.C) {
@@ -79,10 +78,8 @@ __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int
         v[0] = gelu_as(v[0]); v[1] = gelu_as(v[1]); v[2] = gelu_as(v[2]); v[3] = gelu_as(v[3]);
         store4((bf16 *)ep.out + (size_t)m * N + n, v);
     } else if constexpr (EPI == EPI_RESID) {
-        float *r = ep.resid + (size_t)m * N + n;
-        float4 x = *(const float4 *)r;
-        x.x += v[0]; x.y += v[1]; x.z += v[2]; x.w += v[3];
-        *(float4 *)r = x;
+        // rr: the residual values at (m, n..n+3), loaded by the caller
+        *(float4 *)(ep.resid + (size_t)m * N + n) = make_float4(rr.x + v[0], rr.y + v[1], rr.z + v[2], rr.w + v[3]);
     } else {
         store4((bf16 *)ep.out + (size_t)m * N + n, v);
     }
@@ -104,9 +101,9 @@ __device__ __forceinline__ void store8(bf16 *p, const float *v) {
 // the float32 residual).  Same conventions as epilogue4.
 template <int EPI>
 __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, int n, f32x4 a, f32x4 c,
-                                           size_t qkv_base, int hc, float qs, float dq, const float2 *rc) {
+                                           size_t qkv_base, int hc, float qs, float dq, const float2 *rc,
+                                           float4 b0, float4 b1) {
     float v[8] = {a[0], a[1], a[2], a[3], c[0], c[1], c[2], c[3]};
-    const float4 b0 = *(const float4 *)(ep.bias + n), b1 = *(const float4 *)(ep.bias + n + 4);
     const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = v[i] * dq + bb[i];
@@ -330,11 +327,46 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
                 }
             }
         }
+        // Bias of the features this lane stores.  On gfx9 a wait for a load
+        // also waits for every store issued before it, so a load between the
+        // stores puts a store round trip on the path: the bias is loaded
+        // before the first store (where registers allow) or once per column
+        // pair, together with that pair's residual rows.  Tile j covers
+        // features 16j + 4g .. (perm: pair j, j+1 covers 16j + 8g .. +7).
+        constexpr bool PRE_B = !FP8 && (EPI == EPI_QKV || EPI == EPI_GELU || EPI == EPI_STORE);
+        float4 bz[TN];
+        auto load_bias = [&](int j) {
+            bz[j] = *(const float4 *)(ep.bias + n0 + wn * WN + 16 * (j & ~1) +
+                                      (ep.perm ? 8 * g + 4 * (j & 1) : 4 * g + 16 * (j & 1)));
+        };
+        if constexpr (PRE_B) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j) load_bias(j);
+        }
         float mlo = 0.f, mhi = 0.f;
 #pragma unroll
-        for (int j = 0; j < TN; j += 2)
+        for (int j = 0; j < TN; j += 2) {
+            if constexpr (!PRE_B) {
+                load_bias(j);
+                load_bias(j + 1);
+            }
+            // residual rows of this column pair, loaded RI row groups at a
+            // time (one wait per batch; FP8 keeps fewer in registers)
+            constexpr int RI = FP8 ? 2 : TM;
+            float4 rz[TM][2];
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
+                if constexpr (EPI == EPI_RESID) {
+                    if (i % RI == 0) {
+#pragma unroll
+                        for (int ii = i; ii < i + RI; ++ii) {
+                            const int m = min(m0 + wm * WM + 16 * ii + r16, M - 1);
+                            const float *r = ep.resid + (size_t)(m + ep.row0) * N + n0 + wn * WN + 16 * j + 4 * g;
+                            rz[ii][0] = *(const float4 *)r;
+                            rz[ii][1] = *(const float4 *)(r + 16);
+                        }
+                    }
+                }
                 const int m = m0 + wm * WM + 16 * i + r16;
                 const long mg = (long)m + ep.row0;
                 float a = 0.f;
@@ -342,12 +374,18 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
                     if (ep.perm) {
                         const int n = n0 + wn * WN + 16 * j + 8 * g;
                         a = epilogue8<EPI>(ep, N, mg, n, acc[j][i], acc[j + 1][i], qkv_base, n - part * ep.C, qs,
-                                           dq[i], rc[i]);
+                                           dq[i], rc[i], bz[j], bz[j + 1]);
                     } else {
                         const int n = n0 + wn * WN + 16 * j + 4 * g;
-                        a = fmaxf(epilogue4<EPI>(ep, N, mg, n, acc[j][i], qkv_base, n - part * ep.C, qs, dq[i]),
+                        float4 r0 = {}, r1 = {};
+                        if constexpr (EPI == EPI_RESID) {
+                            r0 = rz[i][0];
+                            r1 = rz[i][1];
+                        }
+                        a = fmaxf(epilogue4<EPI>(ep, N, mg, n, acc[j][i], qkv_base, n - part * ep.C, qs, dq[i],
+                                                 bz[j], r0),
                                   epilogue4<EPI>(ep, N, mg, n + 16, acc[j + 1][i], qkv_base, n + 16 - part * ep.C,
-                                                 qs, dq[i]));
+                                                 qs, dq[i], bz[j + 1], r1));
                     }
                 }
                 acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -360,6 +398,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
                                   __float_as_uint(a));
                 }
             }
+        }
         if (ep.out_amax) {
             mlo = wave_max(mlo);
             mhi = wave_max(mhi);
