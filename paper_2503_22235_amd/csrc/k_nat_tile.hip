@@ -275,32 +275,40 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
 #pragma unroll
     for (int e = 0; e < 8; ++e) ones[e] = __builtin_bit_cast(bf16, (unsigned short)0x3f80);
 
-    // K fragments ping-pong between two register sets: half hf of a level
-    // uses kreg[hf] while the next chunk is in flight into the other set.
-    bf16x8 kreg[2][2][2];
+    // K fragments rotate through four register sets, two chunks ahead:
+    // chunk (hz, hf) uses kreg[2 (hz & 1) + hf] while chunk (hz + 1, hf) is
+    // in flight into kreg[2 (~hz & 1) + hf] (the last level reloads itself).
+    // Levels go two per loop iteration so that the set indices are constants.
+    bf16x8 kreg[4][2][2];
 #pragma unroll
     for (int G = 0; G < 2; ++G)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j) {
             kreg[0][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(krs, kofs[j][G], 0, 0));
+            kreg[1][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(krs, kofs[2 + j][G], 0, 0));
+        }
 
-    for (int hz = 0; hz < zn; ++hz) {
+    for (int hz0 = 0; hz0 < zn; hz0 += 2)
+#pragma unroll
+    for (int lv = 0; lv < 2; ++lv) {
+        const int hz = hz0 + lv;
+        if (hz >= zn) break;                 // uniform
         const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
         const unsigned char *vz0 = Vtb + vbase0 + hz * vslab;
         const unsigned char *vz1 = Vtb + vbase1 + hz * vslab;
         const int tbh = tb_lane + hz * BY * XT;
 #pragma unroll
         for (int hf = 0; hf < 2; ++hf) {
-            {   // next chunk: (hz, 1) or (hz + 1, 0); the last level reloads itself
-                const int nh = hf ^ 1;
+            const int ks = 2 * lv + hf;          // this chunk's K set
+            {   // chunk (hz + 1, hf) into the set of (hz - 1, hf)
                 // uniform; readfirstlane lets the scalar offset take it directly
-                const int soff = __builtin_amdgcn_readfirstlane((hf ? min(hz + 1, zn - 1) : hz) * kslab);
+                const int soff = __builtin_amdgcn_readfirstlane(min(hz + 1, zn - 1) * kslab);
 #pragma unroll
                 for (int G = 0; G < 2; ++G)
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        kreg[nh][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
-                            krs, kofs[2 * nh + j][G], soff, 0));
+                        kreg[ks ^ 2][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
+                            krs, kofs[2 * hf + j][G], soff, 0));
             }
             // bias + mask tile (shared by both groups); masked rows read
             // the run of -inf past the table
@@ -319,7 +327,7 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
             for (int G = 0; G < 2; ++G)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    s[G][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kreg[hf][G][j], qf[G], binit[j], 0, 0, 0);
+                    s[G][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kreg[ks][G][j], qf[G], binit[j], 0, 0, 0);
                     if constexpr (!QSCALED) {
 #pragma unroll
                         for (int i = 0; i < 4; ++i) s[G][j][i] *= p.qscale;
