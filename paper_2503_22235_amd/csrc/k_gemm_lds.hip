@@ -413,6 +413,11 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
 #endif
 }
 
+// Feature tiles per workgroup for 256-wide tiles: the block's QKV (N = 3C =
+// 1536) and MLP1 (N = 4C = 2048) GEMMs at C = 512 run fastest with 3 and 4
+// (measured); other N of 1536 or more take 2, smaller N take 1.
+inline int wide_tpw(int N) { return N == 1536 ? 3 : (N == 2048 ? 4 : (N >= 1536 ? 2 : 1)); }
+
 template <int BM, int BN, int BKB, int STAGES, int WGM, int WGN, int OCC, bool FP8>
 hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                       hipStream_t stream, int tpw_default = 1) {
@@ -488,8 +493,9 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
                            hipStream_t stream) {
     // Default for N a multiple of 256: 256x256 tiles, 8 waves (4 x 2, wave
     // tile 64 x 128), 2 stages of 64 KB, one workgroup per CU; wide outputs
-    // (six or more feature tiles) walk two feature tiles per workgroup so the
-    // second tile's loads overlap the first one's epilogue.  Other N: 128x128
+    // (six or more feature tiles) walk several feature tiles per workgroup
+    // (wide_tpw) so that each next tile's loads overlap the previous tile's
+    // epilogue and the activation tile is reused from L2.  Other N: 128x128
     // tiles, 2 stages, two workgroups per CU.  WM_GEMM_CFG selects other
     // shapes for tuning.
     static const int cfg = [] {
@@ -504,7 +510,7 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
     case 9: return launch_cfg<256, 128, 64, 3, 4, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
     default: break;
     }
-    if (n256) return launch_cfg<256, 256, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, N >= 1536 ? 2 : 1);
+    if (n256) return launch_cfg<256, 256, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, wide_tpw(N));
     return launch_cfg<128, 128, 128, 2, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
 }
 
@@ -517,7 +523,7 @@ hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, Ep
         return v ? atoi(v) : -1;
     }();
     if (N % 256 == 0 && cfg != 0)
-        return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, N >= 1536 ? 2 : 1);
+        return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, wide_tpw(N));
     return launch_cfg<128, 128, 128, 2, 2, 2, 2, true>(A, W, M, N, K, epi, ep, stream);
 }
 
