@@ -62,6 +62,7 @@ CFG2 = Grid(Z=8, Y=90, X=180, C=512, heads=16, Kz=5, Ky=7, Kx=7)
 _STREAM_STATE = 1
 _STREAM_PARAM = 2
 _STREAM_ARRIVAL = 3
+_STREAM_SMOOTH = 4
 
 
 def block_param_layout(g: Grid):
@@ -102,6 +103,36 @@ def latent_state(g: Grid, B: int = 1, seed: int = 0, index0: int = 0) -> np.ndar
     for b in range(B):
         r = _rng(seed, _STREAM_STATE, index0 + b)
         out[b] = r.standard_normal((g.Z, g.Y, g.X, g.C)).astype(np.float32)
+    return out
+
+
+def smooth_state(g: Grid, B: int = 1, seed: int = 0, noise: float = 0.1) -> np.ndarray:
+    """Latent states [B, Z, Y, X, C] float32 with large-scale structure: per
+    channel, a sum of low-order modes, cos(m lon + phase) cos(n colat + phase)
+    with m = 1..3 around the periodic longitude and n = 1..2 in colatitude,
+    times a level profile cos(l pi (z + 1/2) / Z), l = 0..1, with random
+    amplitudes; scaled to unit variance per channel, plus noise * N(0, 1).
+    A stand-in for smooth analysis fields (FP8 scales see a realistic
+    dynamic range).
+    """
+    lon = 2.0 * np.pi * np.arange(g.X) / g.X
+    colat = np.pi * (np.arange(g.Y) + 0.5) / g.Y
+    lev = np.pi * (np.arange(g.Z) + 0.5) / g.Z
+    out = np.empty((B, g.Z, g.Y, g.X, g.C), dtype=np.float32)
+    for b in range(B):
+        r = _rng(seed, _STREAM_SMOOTH, b)
+        f = np.zeros((g.Z, g.Y, g.X, g.C), dtype=np.float32)
+        for m in (1, 2, 3):
+            for n in (1, 2):
+                for l in (0, 1):
+                    amp = r.standard_normal(g.C)
+                    pl, pc = r.uniform(0, 2 * np.pi, g.C), r.uniform(0, 2 * np.pi, g.C)
+                    fz = (np.cos(l * lev)[:, None] * amp).astype(np.float32)          # [Z, C]
+                    fy = np.cos(n * colat[:, None] + pc).astype(np.float32)            # [Y, C]
+                    fx = np.cos(m * lon[:, None] + pl).astype(np.float32)              # [X, C]
+                    f += (fz[:, None, :] * fy[None, :, :])[:, :, None, :] * fx[None, None, :, :]
+        f /= f.reshape(-1, g.C).std(axis=0) + 1e-12
+        out[b] = (f + noise * r.standard_normal(f.shape)).astype(np.float32)
     return out
 
 
