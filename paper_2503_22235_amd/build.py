@@ -21,12 +21,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
 
 
-# Per-file extra flags.  The attention kernels never create NaNs (masked
-# scores are -inf, reference maxima start finite), so their max reductions
-# can skip IEEE NaN canonicalisation.
-EXTRA = {
-    "k_nat_tile.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"],
-}
+# Per-file extra flags (none at present).  Flags that change a function's
+# floating-point attributes, such as -mno-amdgpu-ieee, also stop the device
+# library's helpers (work-item ids, 24-bit multiplies) from being inlined.
+EXTRA = {}
 
 
 def sources():

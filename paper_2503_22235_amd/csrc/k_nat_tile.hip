@@ -61,6 +61,9 @@ __device__ __forceinline__ void *uniform_ptr(const void *p) {
     return (void *)(((unsigned long long)hi << 32) | lo);
 }
 
+// 24-bit unsigned product (v_mul_u32_u24): both operands must be below 2^24.
+__device__ __forceinline__ unsigned mul24(unsigned a, unsigned b) { return (a & 0xffffffu) * (b & 0xffffffu); }
+
 __device__ __forceinline__ float xmax16_32(float v) {
     auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
     v = max2f(__uint_as_float(a[0]), __uint_as_float(a[1]));
@@ -140,6 +143,14 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         const uint4 *src = (const uint4 *)(p.tbl_ws + (size_t)h * TBLP);
         for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
     }
+    // 32-bit byte offsets within a head's K or V plane: the launcher keeps
+    // the plane below 2 GiB and a lat row of it below 2^24 bytes, so the row
+    // and column products are 24-bit multiplies.
+    const unsigned utsb = (unsigned)p.ts * 2u;                   // token
+    const unsigned usrow = (unsigned)p.X * utsb;                 // lat row
+    const unsigned uslab = (unsigned)p.Y * usrow;                // level
+    const unsigned urow0 = (unsigned)zlo * uslab + (unsigned)ylo * usrow;   // halo origin (lon 0)
+
     // ---- V halo, transposed: slot (hz, hy, hx) at (hz YR + hy) XW + hx.
     // Item = (slot pair, 16-byte chunk c) of one halo row (level, lat): the
     // 32 items of a row go to 32 consecutive threads (4 lanes read the 2 x 64
@@ -156,31 +167,33 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         int xb = xlo + (2 * pr + 1 < TX + KX - 1 ? 2 * pr + 1 : 0);
         xa = xa < 0 ? xa + p.X : (xa >= p.X ? xa - p.X : xa);
         xb = xb < 0 ? xb + p.X : (xb >= p.X ? xb - p.X : xb);
+        const unsigned oa = mul24((unsigned)xa, utsb) + 16u * c, ob = mul24((unsigned)xb, utsb) + 16u * c;
+        const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(vb), 0, 0x7ffffffe, 0x00020000);
         unsigned *Vt32 = (unsigned *)Vtb + (8 * c) * (VS >> 1) + pr;
         for (int rb = rb0; rb < nrows; rb += 8 * LD_BATCH) {
             uint4 v0[LD_BATCH], v1[LD_BATCH];
 #pragma unroll
             for (int u = 0; u < LD_BATCH; ++u) {
-                const int row = min(rb + 8 * u, nrows - 1);
-                const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
-                const long rtok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X;
-                v0[u] = *(const uint4 *)(vb + (size_t)(rtok + xa) * p.ts + 8 * c);
-                v1[u] = *(const uint4 *)(vb + (size_t)(rtok + xb) * p.ts + 8 * c);
+                const unsigned row = (unsigned)min(rb + 8 * u, nrows - 1);
+                const unsigned hz = mul24(row, ym) >> 16, hy = row - mul24(hz, (unsigned)yn);
+                const unsigned ro = urow0 + hz * uslab + mul24(hy, usrow);
+                v0[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(vrs, ro + oa, 0, 0));
+                v1[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(vrs, ro + ob, 0, 0));
             }
 #pragma unroll
             for (int u = 0; u < LD_BATCH; ++u) {
                 const int row = rb + 8 * u;
                 if (row < nrows) {
-                    const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
-                    unsigned *vrow = Vt32 + (hz * YR + hy) * (XW / 2);
-                    vrow[0 * (VS >> 1)] = (v0[u].x & 0xffffu) | (v1[u].x << 16);
-                    vrow[1 * (VS >> 1)] = (v0[u].x >> 16) | (v1[u].x & 0xffff0000u);
-                    vrow[2 * (VS >> 1)] = (v0[u].y & 0xffffu) | (v1[u].y << 16);
-                    vrow[3 * (VS >> 1)] = (v0[u].y >> 16) | (v1[u].y & 0xffff0000u);
-                    vrow[4 * (VS >> 1)] = (v0[u].z & 0xffffu) | (v1[u].z << 16);
-                    vrow[5 * (VS >> 1)] = (v0[u].z >> 16) | (v1[u].z & 0xffff0000u);
-                    vrow[6 * (VS >> 1)] = (v0[u].w & 0xffffu) | (v1[u].w << 16);
-                    vrow[7 * (VS >> 1)] = (v0[u].w >> 16) | (v1[u].w & 0xffff0000u);
+                    const unsigned hz = mul24((unsigned)row, ym) >> 16, hy = (unsigned)row - mul24(hz, (unsigned)yn);
+                    unsigned *vrow = Vt32 + mul24(mul24(hz, (unsigned)YR) + hy, (unsigned)(XW / 2));
+                    vrow[0 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].x, v0[u].x, 0x05040100u);
+                    vrow[1 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].x, v0[u].x, 0x07060302u);
+                    vrow[2 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].y, v0[u].y, 0x05040100u);
+                    vrow[3 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].y, v0[u].y, 0x07060302u);
+                    vrow[4 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].z, v0[u].z, 0x05040100u);
+                    vrow[5 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].z, v0[u].z, 0x07060302u);
+                    vrow[6 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].w, v0[u].w, 0x05040100u);
+                    vrow[7 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].w, v0[u].w, 0x07060302u);
                 }
             }
         }
@@ -240,7 +253,7 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         for (int G = 0; G < 2; ++G) {
             int xk = xlo + (r16 & 7) + GX * (gxa + G);
             xk = xk < 0 ? xk + p.X : (xk >= p.X ? xk - p.X : xk);
-            kofs[q][G] = (((zlo * p.Y) + ylo + hyk) * p.X + xk) * tsb + 16 * g;
+            kofs[q][G] = (int)(urow0 + mul24((unsigned)hyk, usrow) + mul24((unsigned)xk, utsb)) + 16 * g;
         }
     }
     const int kslab = p.Y * p.X * tsb;
@@ -259,7 +272,7 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         const int xq = x0 + GX * (gxa + G) + xrel;
         act[G] = zq < p.Z && yq < p.Y && xq < p.X;
         const int xc = min(xq, p.X - 1);
-        qtok[G] = ((long)zc * p.Y + yc) * p.X + xc;
+        qtok[G] = (long)mul24(mul24((unsigned)zc, (unsigned)p.Y) + (unsigned)yc, (unsigned)p.X) + xc;
         qf[G] = *(const bf16x8 *)(qb + qtok[G] * p.ts + 8 * g);
     }
 
@@ -829,8 +842,10 @@ size_t nat_tile_lds_bytes(const NatArgs &a) {
     if (!known) return 0;
     if (a.X < TX + a.Kx - 1) return 0;     // the lon halo must not wrap onto itself
     if (!a.tbl_ws) return 0;
-    // K is addressed with 32-bit byte offsets from the state's base
+    // K and V are addressed with 32-bit byte offsets from the state's base,
+    // rows and tokens with 24-bit products
     if ((long)a.Z * a.Y * a.X * a.ts * 2 >= (1L << 31)) return 0;
+    if ((long)a.X * a.ts * 2 >= (1L << 24) || (long)a.Z * a.Y >= (1L << 24)) return 0;
     const int zw = max_halo(a.Z, a.Kz, TZ), yr = std::max(max_halo(a.Y, a.Ky, TY), YR_MIN);
     return a.amax ? tile_lds_fp8(a.Kz, a.Ky, zw, yr) : tile_lds(a.Kz, a.Ky, zw, yr);
 }
