@@ -71,6 +71,17 @@ __device__ __forceinline__ float xmax16_32(float v) {
     return max2f(__uint_as_float(b[0]), __uint_as_float(b[1]));
 }
 
+// Division of a workgroup id by the tile counts and the head count:
+// m = ceil(2^32 / d) (0 for d = 1) gives floor(t / d) = mulhi(t, m) exactly
+// while t d < 2^32, which the launcher checks.
+struct TileDiv { unsigned mx, my, mz, mh; };
+__device__ __forceinline__ unsigned mdiv(unsigned t, unsigned m) { return m ? __umulhi(t, m) : t; }
+inline unsigned div_magic(unsigned d) { return d <= 1 ? 0u : (unsigned)(((1ull << 32) + d - 1) / d); }
+inline TileDiv tile_div(const NatArgs &a) {
+    return TileDiv{div_magic((a.X + TX - 1) / TX), div_magic((a.Y + TY - 1) / TY), div_magic((a.Z + TZ - 1) / TZ),
+                   div_magic(a.H)};
+}
+
 // QSCALED: q already carries the factor log2(e)/sqrt(d) (the block path folds
 // it into the QKV projection); otherwise scores are scaled after the MFMA and
 // the bias table is stored divided by that scale.
@@ -99,7 +110,7 @@ __global__ void nat_bias_prep(NatArgs p) {
 }
 
 template <int KZ, int KY, int KX, bool QSCALED>
-__global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, int YR) {
+__global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, int YR, TileDiv dm) {
     constexpr int RX = (KX - 1) / 2;
     constexpr int BY = 2 * KY - 1;
     constexpr int TBL = (2 * KZ - 1) * BY * XT;    // bias table entries
@@ -120,12 +131,14 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
     const int L = blockIdx.x;
     const int id = (L & 7) * per + (L >> 3);
     if (id >= total) return;
-    int t = id;
-    const int tx = t % ntx; t /= ntx;
-    const int ty = t % nty; t /= nty;
-    const int tz = t % ntz; t /= ntz;
-    const int h = t % p.H;
-    const int b = t / p.H;
+    // (tile x, y, z, head, state) from id by multiply-high divisions on
+    // scalar registers (magic numbers from the launcher)
+    unsigned t = (unsigned)id, q;
+    q = mdiv(t, dm.mx); const int tx = (int)(t - q * (unsigned)ntx); t = q;
+    q = mdiv(t, dm.my); const int ty = (int)(t - q * (unsigned)nty); t = q;
+    q = mdiv(t, dm.mz); const int tz = (int)(t - q * (unsigned)ntz); t = q;
+    q = mdiv(t, dm.mh); const int h = (int)(t - q * (unsigned)p.H);
+    const int b = (int)q;
     const int z0 = tz * TZ, y0 = ty * TY, x0 = tx * TX;
 
     int zlo, zn, ylo, yn;
@@ -470,7 +483,7 @@ __global__ void nat_bias_prep_fp8(NatArgs p) {
 }
 
 template <int KZ, int KY, int KX>
-__global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWmax, int YR) {
+__global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWmax, int YR, TileDiv dm) {
     constexpr int RX = (KX - 1) / 2;
     constexpr int BY = 2 * KY - 1;
     constexpr int TBL = (2 * KZ - 1) * BY * XT;
@@ -489,12 +502,14 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
     const int L = blockIdx.x;
     const int id = (L & 7) * per + (L >> 3);
     if (id >= total) return;
-    int t = id;
-    const int tx = t % ntx; t /= ntx;
-    const int ty = t % nty; t /= nty;
-    const int tz = t % ntz; t /= ntz;
-    const int h = t % p.H;
-    const int b = t / p.H;
+    // (tile x, y, z, head, state) from id by multiply-high divisions on
+    // scalar registers (magic numbers from the launcher)
+    unsigned t = (unsigned)id, q;
+    q = mdiv(t, dm.mx); const int tx = (int)(t - q * (unsigned)ntx); t = q;
+    q = mdiv(t, dm.my); const int ty = (int)(t - q * (unsigned)nty); t = q;
+    q = mdiv(t, dm.mz); const int tz = (int)(t - q * (unsigned)ntz); t = q;
+    q = mdiv(t, dm.mh); const int h = (int)(t - q * (unsigned)p.H);
+    const int b = (int)q;
     const int z0 = tz * TZ, y0 = ty * TY, x0 = tx * TX;
 
     int zlo, zn, ylo, yn;
@@ -797,7 +812,7 @@ hipError_t launch_tile_q(const NatArgs &a, hipStream_t stream) {
     const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
     const long total = (long)ntiles * a.H * a.B;
     const unsigned grid = (unsigned)(((total + 7) >> 3) << 3);
-    nat_tile_kernel<KZ, KY, KX, QSCALED><<<grid, 256, lds, stream>>>(a, zw, yr);
+    nat_tile_kernel<KZ, KY, KX, QSCALED><<<grid, 256, lds, stream>>>(a, zw, yr, tile_div(a));
     return hipGetLastError();
 }
 
@@ -822,7 +837,7 @@ hipError_t launch_tile_fp8(const NatArgs &a, hipStream_t stream) {
     const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
     const long total = (long)ntiles * a.H * a.B;
     const unsigned grid = (unsigned)(((total + 7) >> 3) << 3);
-    nat_tile_fp8_kernel<KZ, KY, KX><<<grid, 256, lds, stream>>>(a, zw, yr);
+    nat_tile_fp8_kernel<KZ, KY, KX><<<grid, 256, lds, stream>>>(a, zw, yr, tile_div(a));
     return hipGetLastError();
 }
 
@@ -846,6 +861,12 @@ size_t nat_tile_lds_bytes(const NatArgs &a) {
     // rows and tokens with 24-bit products
     if ((long)a.Z * a.Y * a.X * a.ts * 2 >= (1L << 31)) return 0;
     if ((long)a.X * a.ts * 2 >= (1L << 24) || (long)a.Z * a.Y >= (1L << 24)) return 0;
+    {   // workgroup-id divisions by multiply-high (tile_div) are exact while id * d < 2^32
+        const long nt[4] = {(a.X + TX - 1) / TX, (a.Y + TY - 1) / TY, (a.Z + TZ - 1) / TZ, a.H};
+        const long total = nt[0] * nt[1] * nt[2] * a.H * a.B;
+        for (long d : nt)
+            if (total * d >= (1L << 32)) return 0;
+    }
     const int zw = max_halo(a.Z, a.Kz, TZ), yr = std::max(max_halo(a.Y, a.Ky, TY), YR_MIN);
     return a.amax ? tile_lds_fp8(a.Kz, a.Ky, zw, yr) : tile_lds(a.Kz, a.Ky, zw, yr);
 }
