@@ -71,24 +71,31 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // GELU(z) = z * Phi(z) = z/2 * (1 + erf(z / sqrt 2)), with erf from the
-// rational approximation of Abramowitz & Stegun, Handbook of Mathematical
-// Functions, eq. 7.1.26 (Hastings): for x >= 0,
-//   erf(x) = 1 - P(t) exp(-x^2),  P(t) = a1 t + a2 t^2 + a3 t^3 + a4 t^4 + a5 t^5,
-//   t = 1 / (1 + p x),  |error| <= 1.5e-7.
+// approximation of Abramowitz & Stegun, Handbook of Mathematical Functions,
+// eq. 7.1.28 (Hastings): for x >= 0,
+//   erf(x) = 1 - (1 + a1 x + a2 x^2 + ... + a6 x^6)^-16,  |error| <= 3e-7.
 // With x = |z| / sqrt 2 and erf odd, both signs of z collapse to
-//   GELU(z) = max(z, 0) - |z|/2 * P(t) * exp(-z^2 / 2),
-// which needs no sign select; the 1/2 and 1/sqrt 2 are folded into the
-// constants.
+//   GELU(z) = max(z, 0) - |z|/2 * (1 + a1 x + ... + a6 x^6)^-16,
+// one reciprocal and no exponential (transcendentals issue at a quarter of
+// the VALU rate); the 1/sqrt 2 powers are folded into the coefficients.
 __device__ __forceinline__ float gelu_as(float z) {
+    constexpr float r2 = 0.70710678118654752f;
+    constexpr float c1 = 0.0705230784f * r2, c2 = 0.0422820123f * r2 * r2, c3 = 0.0092705272f * r2 * r2 * r2,
+                    c4 = 0.0001520143f * r2 * r2 * r2 * r2, c5 = 0.0002765672f * r2 * r2 * r2 * r2 * r2,
+                    c6 = 0.0000430638f * r2 * r2 * r2 * r2 * r2 * r2;
     const float az = fabsf(z);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, az, 1.0f));
-    float q = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
-    q = fmaf(q, t, 0.5f * 1.421413741f);
-    q = fmaf(q, t, 0.5f * -0.284496736f);
-    q = fmaf(q, t, 0.5f * 0.254829592f);
-    const float s = q * t * az;
-    const float ex = __builtin_amdgcn_exp2f(z * z * (-0.5f * LOG2E));
-    return fmaf(-s, ex, fmaxf(z, 0.0f));
+    float p = fmaf(c6, az, c5);
+    p = fmaf(p, az, c4);
+    p = fmaf(p, az, c3);
+    p = fmaf(p, az, c2);
+    p = fmaf(p, az, c1);
+    p = fmaf(p, az, 1.0f);
+    float r = __builtin_amdgcn_rcpf(p);
+    r *= r;    // ^2
+    r *= r;    // ^4
+    r *= r;    // ^8
+    r *= r;    // ^16
+    return fmaf(-0.5f * az, r, fmaxf(z, 0.0f));
 }
 
 // ---------------------------------------------------------------------------
