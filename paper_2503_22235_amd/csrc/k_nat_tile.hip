@@ -213,10 +213,11 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         if (yn < YR) {
             unsigned *V0 = (unsigned *)Vtb;
             const int gap = (YR - yn) * (XW / 2);              // dword columns per level
+            const unsigned gm = 0xffffffffu / (unsigned)gap + 1u;   // col / gap == mulhi(col, gm) (col * gap < 2^32)
             const int nz = zn * gap * 32;
             for (int e = tid; e < nz; e += 256) {
                 const int d = e & 31, col = e >> 5;
-                const int hz = col / gap, cg = col - hz * gap;
+                const int hz = (int)__umulhi((unsigned)col, gm), cg = col - hz * gap;
                 V0[d * (VS >> 1) + (hz * YR + yn) * (XW / 2) + cg] = 0u;
             }
         }
@@ -525,6 +526,10 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
     const float c = dq_scale(aq) * dq_scale(ak) * p.qscale;     // score unit, log2 domain
     const float mulk = q_mul(ak), mulv = q_mul(av);
     const int tid = threadIdx.x;
+    // 32-bit byte offsets within the head's K and V planes, 24-bit products
+    // (the launcher checks the plane and row sizes)
+    const unsigned utsb = (unsigned)p.ts * 2u, usrow = (unsigned)p.X * utsb, uslab = (unsigned)p.Y * usrow;
+    const unsigned urow0 = (unsigned)zlo * uslab + (unsigned)ylo * usrow;
 
     {
         const uint4 *src = (const uint4 *)(p.tbl_ws + ((size_t)b * p.H + h) * TBLP);
@@ -540,21 +545,23 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
         int xc = xlo + (hx < TX + KX - 1 ? hx : 0);
         xc = xc < 0 ? xc + p.X : (xc >= p.X ? xc - p.X : xc);
         unsigned char *kdst = Ks + hx * 32 + 8 * cc;
+        const unsigned kcol = mul24((unsigned)xc, utsb) + 16u * cc;
+        const __amdgpu_buffer_rsrc_t krs8 = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(kb), 0, 0x7ffffffe, 0x00020000);
         for (int rb = rb0; rb < nrows; rb += 4 * LD_BATCH) {
             uint4 raw[LD_BATCH];
 #pragma unroll
             for (int u = 0; u < LD_BATCH; ++u) {
-                const int row = min(rb + 4 * u, nrows - 1);
-                const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
-                const long rtok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X;
-                raw[u] = *(const uint4 *)(kb + (size_t)(rtok + xc) * p.ts + 8 * cc);
+                const unsigned row = (unsigned)min(rb + 4 * u, nrows - 1);
+                const unsigned hz = mul24(row, ym) >> 16, hy = row - mul24(hz, (unsigned)yn);
+                raw[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                    krs8, urow0 + hz * uslab + mul24(hy, usrow) + kcol, 0, 0));
             }
 #pragma unroll
             for (int u = 0; u < LD_BATCH; ++u) {
                 const int row = rb + 4 * u;
                 if (row < nrows) {
-                    const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
-                    *(uint2 *)(kdst + (hz * YR + hy) * KRS) = bf16x8_to_e4m3(raw[u], mulk);
+                    const unsigned hz = mul24((unsigned)row, ym) >> 16, hy = (unsigned)row - mul24(hz, (unsigned)yn);
+                    *(uint2 *)(kdst + mul24(mul24(hz, (unsigned)YR) + hy, (unsigned)KRS)) = bf16x8_to_e4m3(raw[u], mulk);
                 }
             }
         }
@@ -570,21 +577,26 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
             xs[w] = xc < 0 ? xc + p.X : (xc >= p.X ? xc - p.X : xc);
         }
         unsigned char *vdst = Vt + (8 * cc) * VSB + 4 * qd;
+        unsigned vcol[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) vcol[w] = mul24((unsigned)xs[w], utsb) + 16u * cc;
+        const __amdgpu_buffer_rsrc_t vrs8 = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(vb), 0, 0x7ffffffe, 0x00020000);
         for (int rb = rb0; rb < nrows; rb += 16 * (LD_BATCH / 2)) {
             uint4 raw[LD_BATCH / 2][4];
 #pragma unroll
             for (int u = 0; u < LD_BATCH / 2; ++u) {
-                const int row = min(rb + 16 * u, nrows - 1);
-                const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
-                const long rtok = ((long)(zlo + hz) * p.Y + (ylo + hy)) * p.X;
+                const unsigned row = (unsigned)min(rb + 16 * u, nrows - 1);
+                const unsigned hz = mul24(row, ym) >> 16, hy = row - mul24(hz, (unsigned)yn);
+                const unsigned ro = urow0 + hz * uslab + mul24(hy, usrow);
 #pragma unroll
-                for (int w = 0; w < 4; ++w) raw[u][w] = *(const uint4 *)(vb + (size_t)(rtok + xs[w]) * p.ts + 8 * cc);
+                for (int w = 0; w < 4; ++w)
+                    raw[u][w] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(vrs8, ro + vcol[w], 0, 0));
             }
 #pragma unroll
             for (int u = 0; u < LD_BATCH / 2; ++u) {
                 const int row = rb + 16 * u;
                 if (row < nrows) {
-                    const int hz = (int)(((unsigned)row * ym) >> 16), hy = row - hz * yn;
+                    const unsigned hz = mul24((unsigned)row, ym) >> 16, hy = (unsigned)row - mul24(hz, (unsigned)yn);
                     uint2 cv[4];
 #pragma unroll
                     for (int w = 0; w < 4; ++w) cv[w] = bf16x8_to_e4m3(raw[u][w], mulv);
@@ -597,7 +609,7 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
                     const unsigned lo23b = __builtin_amdgcn_perm(cv[3].y, cv[2].y, 0x05010400u);
                     const unsigned hi01b = __builtin_amdgcn_perm(cv[1].y, cv[0].y, 0x07030602u);
                     const unsigned hi23b = __builtin_amdgcn_perm(cv[3].y, cv[2].y, 0x07030602u);
-                    unsigned char *dst = vdst + (hz * YR + hy) * XW;
+                    unsigned char *dst = vdst + mul24(mul24(hz, (unsigned)YR) + hy, (unsigned)XW);
                     *(unsigned *)(dst + 0 * VSB) = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
                     *(unsigned *)(dst + 1 * VSB) = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
                     *(unsigned *)(dst + 2 * VSB) = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
@@ -614,14 +626,16 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
     // every window, whose weight is 0; 0 x code must stay 0)
     if (yn < YR) {
         const int kgap = (YR - yn) * KRS / 4;                 // dwords per level (K)
+        const unsigned km = 0xffffffffu / (unsigned)kgap + 1u;   // e / kgap == mulhi(e, km) (e * kgap < 2^32)
         for (int e = tid; e < zn * kgap; e += 256) {
-            const int hz = e / kgap, o = e - hz * kgap;
+            const int hz = (int)__umulhi((unsigned)e, km), o = e - hz * kgap;
             ((unsigned *)(Ks + (hz * YR + yn) * KRS))[o] = 0u;
         }
         const int vgap = (YR - yn) * XW / 4;                  // dwords per level and channel (V)
+        const unsigned vm = 0xffffffffu / (unsigned)vgap + 1u;   // col / vgap == mulhi(col, vm) (col * vgap < 2^32)
         for (int e = tid; e < 32 * zn * vgap; e += 256) {
             const int d = e & 31, col = e >> 5;
-            const int hz = col / vgap, o = col - hz * vgap;
+            const int hz = (int)__umulhi((unsigned)col, vm), o = col - hz * vgap;
             ((unsigned *)(Vt + d * VSB + (hz * YR + yn) * XW))[o] = 0u;
         }
     }
@@ -667,7 +681,7 @@ __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWm
         const int xq = x0 + GX * (gxa + G) + xrel;
         act[G] = zq < p.Z && yq < p.Y && xq < p.X;
         const int xc = min(xq, p.X - 1);
-        qtok[G] = ((long)zc * p.Y + yc) * p.X + xc;
+        qtok[G] = (long)mul24(mul24((unsigned)zc, (unsigned)p.Y) + (unsigned)yc, (unsigned)p.X) + xc;
         const uint2 q8 = bf16x8_to_e4m3(*(const uint4 *)(qb + qtok[G] * p.ts + 8 * g), mulq);
         qf[G] = (long)(((unsigned long long)q8.y << 32) | q8.x);
     }
