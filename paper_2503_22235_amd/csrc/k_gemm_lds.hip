@@ -161,6 +161,42 @@ __device__ __forceinline__ void wait_stages(int rem) {
     }
 }
 
+// The MFMAs of one K stage for a wave's TM x TN tiles.  FIRST: the stage is
+// the tile's first, so its first k-step adds to zero instead of acc.
+template <bool FIRST, bool FP8, int TM, int TN, int KSTEPS, int BKB>
+__device__ __forceinline__ void mma_stage(const unsigned char *sb, const int *aoff, const int *woff,
+                                          f32x4 (&acc)[TN][TM]) {
+    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+        if constexpr (FP8) {
+            long af[TM], wf[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) af[i] = *(const long *)(sb + aoff[ks] + 16 * i * BKB);
+#pragma unroll
+            for (int j = 0; j < TN; ++j) wf[j] = *(const long *)(sb + woff[ks] + 16 * j * BKB);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(wf[j], af[i], FIRST && ks == 0 ? zero : acc[j][i],
+                                                                           0, 0, 0);
+        } else {
+            bf16x8 af[TM], wf[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sb + aoff[ks] + 16 * i * BKB);
+#pragma unroll
+            for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sb + woff[ks] + 16 * j * BKB);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af[i], FIRST && ks == 0 ? zero : acc[j][i],
+                                                                        0, 0, 0);
+        }
+    }
+}
+
 // FP8: operands are e4m3 bytes (128 k-values per 128-byte stage, MFMA
 // 16x16x32 fp8 with 8-byte fragments); the epilogue dequantizes per row.
 // WGM x WGN waves tile the BM x BN output; OCC workgroups share a CU.
@@ -227,6 +263,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         }
     };
 
+    constexpr bool ZSTART = !FP8 && EPI != EPI_QKV_ROPE;
     f32x4 acc[TN][TM];
 #pragma unroll
     for (int j = 0; j < TN; ++j)
@@ -264,32 +301,12 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
             __builtin_amdgcn_s_barrier();
             if (st + AHEAD < S) issue(st + AHEAD, (st + AHEAD) % STAGES);
             const unsigned char *sb = smem + (st % STAGES) * STAGE_BYTES;
-#pragma unroll
-            for (int ks = 0; ks < KSTEPS; ++ks) {
-                if constexpr (FP8) {
-                    long af[TM], wf[TN];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i) af[i] = *(const long *)(sb + aoff[ks] + 16 * i * BKB);
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) wf[j] = *(const long *)(sb + woff[ks] + 16 * j * BKB);
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-#pragma unroll
-                        for (int i = 0; i < TM; ++i)
-                            acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(wf[j], af[i], acc[j][i], 0, 0, 0);
-                } else {
-                    bf16x8 af[TM], wf[TN];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sb + aoff[ks] + 16 * i * BKB);
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sb + woff[ks] + 16 * j * BKB);
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-#pragma unroll
-                        for (int i = 0; i < TM; ++i)
-                            acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af[i], acc[j][i], 0, 0, 0);
-                }
-            }
+            // ZSTART: a tile's first k-step starts its accumulators from an
+            // inline zero operand instead of registers cleared in the previous
+            // epilogue (not for the FP8 and rotary variants, whose extra
+            // registers would spill with a second copy of the stage code)
+            if (ZSTART && kt == 0) mma_stage<ZSTART, FP8, TM, TN, KSTEPS, BKB>(sb, aoff, woff, acc);
+            else mma_stage<false, FP8, TM, TN, KSTEPS, BKB>(sb, aoff, woff, acc);
         }
         const int n0 = (tn0 + t) * BN;
         // a feature tile never straddles Q/K/V (C is a multiple of BN)
@@ -388,8 +405,10 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
                                                  qs, dq[i], bz[j + 1], r1));
                     }
                 }
-                acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
-                acc[j + 1][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if constexpr (!ZSTART) {
+                    acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+                    acc[j + 1][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+                }
                 if (ep.out_amax) {
                     if (srow[i] == s_lo) mlo = fmaxf(mlo, a);
                     else if (srow[i] == s_lo + 1) mhi = fmaxf(mhi, a);
