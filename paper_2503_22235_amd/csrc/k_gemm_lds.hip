@@ -64,8 +64,10 @@ __device__ __forceinline__ void store4(bf16 *p, f32x4 v) {
 template <int EPI>
 __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int n, f32x4 v,
                                            size_t qkv_base, int hc, float qs, float dq, float4 b, float4 rr) {
-    v[0] *= dq; v[1] *= dq; v[2] *= dq; v[3] *= dq;
-    v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
+    // explicit FMAs: the rounding of every element must not depend on how
+    // the compiler contracts each unrolled copy (a token's result must not
+    // depend on its position in the tile, i.e. on the batch)
+    v[0] = fmaf(v[0], dq, b.x); v[1] = fmaf(v[1], dq, b.y); v[2] = fmaf(v[2], dq, b.z); v[3] = fmaf(v[3], dq, b.w);
     if constexpr (epi_qkv(EPI)) {
         if (EPI == EPI_QKV_ROPE && n < 2 * ep.C) {
             float r[4] = {v[0], v[1], v[2], v[3]};
@@ -106,15 +108,15 @@ __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, in
     float v[8] = {a[0], a[1], a[2], a[3], c[0], c[1], c[2], c[3]};
     const float bb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = v[i] * dq + bb[i];
+    for (int i = 0; i < 8; ++i) v[i] = fmaf(v[i], dq, bb[i]);    // explicit FMA, as in epilogue4
     if constexpr (epi_qkv(EPI)) {
         if (EPI == EPI_QKV_ROPE && n < 2 * ep.C) {
             // rc: (cos, sin) of this row's 4 channel pairs (hc & 31) / 2 ..
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const float a0 = v[2 * i], a1 = v[2 * i + 1];
-                v[2 * i] = a0 * rc[i].x - a1 * rc[i].y;
-                v[2 * i + 1] = a0 * rc[i].y + a1 * rc[i].x;
+                v[2 * i] = fmaf(a0, rc[i].x, -(a1 * rc[i].y));
+                v[2 * i + 1] = fmaf(a0, rc[i].y, a1 * rc[i].x);
             }
         }
 #pragma unroll

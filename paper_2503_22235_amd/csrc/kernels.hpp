@@ -67,8 +67,8 @@ __device__ __forceinline__ void rope_rotate(float *v, int cnt, int e, long mg, c
         const int row = p < 4 ? z : (p < 10 ? ep.rZ + y : ep.rZ + ep.rY + x);
         const float2 cs = *(const float2 *)(ep.rope + 2 * (row * 16 + p));
         const float a = v[2 * i], b = v[2 * i + 1];
-        v[2 * i] = a * cs.x - b * cs.y;
-        v[2 * i + 1] = a * cs.y + b * cs.x;
+        v[2 * i] = fmaf(a, cs.x, -(b * cs.y));      // explicit FMAs: position-independent rounding
+        v[2 * i + 1] = fmaf(a, cs.y, b * cs.x);
     }
 }
 
