@@ -45,7 +45,10 @@ __global__ __launch_bounds__(256) void ln_amax_kernel(const float *__restrict__ 
     const float mean = wave_sum(s) * (1.0f / C);
     float q = 0.f;
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) q += (v[i] - mean) * (v[i] - mean);
+    for (int i = 0; i < VPT; ++i) {
+        const float d = v[i] - mean;
+        q = fmaf(d, d, q);            // explicit: both passes get the same statistics
+    }
     const float rstd = 1.0f / sqrtf(wave_sum(q) * (1.0f / C) + eps);
     float m = 0.f;
 #pragma unroll
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(256) void ln_amax_kernel(const float *__restrict__ 
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int c = 2 * (j * 64 + lane) + u;
-            m = fmaxf(m, fabsf((v[2 * j + u] - mean) * rstd * gamma[c] + beta[c]));
+            m = fmaxf(m, fabsf(fmaf((v[2 * j + u] - mean) * rstd, gamma[c], beta[c])));
         }
     m = wave_max(m);
     if (lane == 0) atomicMax(amax + (blockIdx.x % AMAX_SHARDS) * AMAX_STRIDE + row / T, __float_as_uint(m));
@@ -92,15 +95,19 @@ __global__ __launch_bounds__(256) void ln_quant_kernel(const float *__restrict__
     const float mean = wave_sum(s) * (1.0f / C);
     float q = 0.f;
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) q += (v[i] - mean) * (v[i] - mean);
+    for (int i = 0; i < VPT; ++i) {
+        const float d = v[i] - mean;
+        q = fmaf(d, d, q);            // explicit: both passes get the same statistics
+    }
     const float rstd = 1.0f / sqrtf(wave_sum(q) * (1.0f / C) + eps);
     const float inv = inv_scale(amax[row / T]);
     unsigned char *o = out + (size_t)row * C;
 #pragma unroll
     for (int j = 0; j < VPT / 2; ++j) {
         const int c = 2 * (j * 64 + lane);
-        const float y0 = ((v[2 * j] - mean) * rstd * gamma[c] + beta[c]) * inv;
-        const float y1 = ((v[2 * j + 1] - mean) * rstd * gamma[c + 1] + beta[c + 1]) * inv;
+        // explicit FMAs: the same value as the amax pass, whatever the contraction
+        const float y0 = fmaf((v[2 * j] - mean) * rstd, gamma[c], beta[c]) * inv;
+        const float y1 = fmaf((v[2 * j + 1] - mean) * rstd, gamma[c + 1], beta[c + 1]) * inv;
         const unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(y0), clamp448(y1), 0, false);
         *(unsigned short *)(o + c) = (unsigned short)(w & 0xffffu);
     }

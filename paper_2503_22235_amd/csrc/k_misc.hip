@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict_
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             const float d = v[r][i] - mean;
-            q += d * d;
+            q = fmaf(d, d, q);
         }
         const float var = wave_sum(q) * (1.0f / C);
         const float rstd = 1.0f / sqrtf(var + eps);
@@ -57,7 +57,9 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict_
             const int base = (j * 64 + lane) * W;
             float y[W];
 #pragma unroll
-            for (int t = 0; t < W; ++t) y[t] = (v[r][W * j + t] - mean) * rstd * gamma[base + t] + beta[base + t];
+            // explicit FMA: the rounding must not depend on the row's slot in
+            // the unrolled row loop (its position depends on the batch)
+            for (int t = 0; t < W; ++t) y[t] = fmaf((v[r][W * j + t] - mean) * rstd, gamma[base + t], beta[base + t]);
             if constexpr (OBF) {
                 bf16 *o = (bf16 *)out + (size_t)row * C + base;
                 if constexpr (W == 4) {
