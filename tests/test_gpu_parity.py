@@ -273,6 +273,27 @@ def test_step_small_config_and_batch_invariance(env, prec):
     p.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_block_batch_invariance_odd_token_count(env, prec):
+    """T = 3 x 9 x 15 = 405 tokens (odd): rows of the second and third states
+    land at other positions within GEMM tiles and LayerNorm row pairs than
+    when each state runs alone; every precision must still give each state
+    bit for bit what it gets alone (rounding may not depend on the position)."""
+    wm, torch, ctx = env
+    g = S.Grid(Z=3, Y=9, X=15, C=128, heads=4, Kz=3, Ky=5, Kx=5)
+    params = S.processor_params(g, 2, 1)
+    x = S.latent_state(g, 3, 4)
+    say("odd-T batch invariance", prec)
+    p = wm.wm_processor_create(ctx, g, 2, 4, prec, params)
+    xb = torch.from_numpy(x).cuda()
+    wm.wm_processor_step(ctx, p, 3, xb)
+    for b in range(3):
+        xs = torch.from_numpy(x[b:b + 1].copy()).cuda()
+        wm.wm_processor_step(ctx, p, 1, xs)
+        assert torch.equal(xb[b:b + 1], xs), f"state {b}: result depends on the batch"
+    p.close()
+
+
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec", [0, 1])
 def test_blocks_full_size_sampled(env, prec):
