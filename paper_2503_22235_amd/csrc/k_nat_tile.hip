@@ -298,9 +298,11 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
         mref[G] = -1e30f;
         thr[G] = -1e30f;
     }
-    bf16x8 ones;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) ones[e] = __builtin_bit_cast(bf16, (unsigned short)0x3f80);
+    // all-ones operand of the row-sum MFMA, kept in vector registers (the
+    // empty asm hides the constant, so it is not rematerialized per chunk)
+    uint4 ones_u = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);
+    asm volatile("" : "+v"(ones_u.x), "+v"(ones_u.y), "+v"(ones_u.z), "+v"(ones_u.w));
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, ones_u);
 
     // K fragments rotate through four register sets, two chunks ahead:
     // chunk (hz, hf) uses kreg[2 (hz & 1) + hf] while chunk (hz + 1, hf) is
