@@ -80,10 +80,18 @@ def step_flops(g, nb=8, B=1, mlp=4):
     return nb * T * (2 * (3 + 1 + 2 * mlp) * g.C * g.C + 4 * g.C * kvol)
 
 
-def kernel_source_hash():
+# The serving loop's host scheduler launches no kernel of its own and does not
+# change how the block's kernels are launched, so it is left out of the hash.
+HASH_EXCLUDE = ("serve.cpp",)
+
+
+def kernel_source_hash(d=None):
+    """Hash of the sources that define the block's kernels and their launches."""
     h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2503_22235_amd", "csrc")
+    d = d or os.path.join(ROOT, "paper_2503_22235_amd", "csrc")
     for f in sorted(os.listdir(d)):
+        if f in HASH_EXCLUDE:
+            continue
         h.update(f.encode())
         h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]

@@ -22,6 +22,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <exception>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -265,7 +266,15 @@ struct wm_server {
         std::unique_lock<std::mutex> lk(mu);
         while (!stop) {
             bool prog = false;
-            if (err_code == WM_OK) prog = step_once(lk);
+            if (err_code == WM_OK) {
+                try {
+                    prog = step_once(lk);
+                } catch (const std::exception &ex) {   // host allocation inside an iteration
+                    if (!lk.owns_lock()) lk.lock();
+                    err_code = WM_ENOMEM;
+                    snprintf(err_msg, sizeof err_msg, "scheduler: %s", ex.what());
+                }
+            }
             if (!prog) cv.wait_for(lk, std::chrono::microseconds(200));
         }
     }
@@ -353,12 +362,12 @@ int wm_serve_submit(wm_server *s, const float *x0_host, int lead_hours, uint64_t
     if (!r) return fail(WM_ENOMEM, "request allocation");
     try {
         r->host_in.assign(x0_host, x0_host + s->elems);
+        r->sched.resize(greedy_schedule(lead_hours, nullptr, 0));
     } catch (...) {
         delete r;
-        return fail(WM_ENOMEM, "request state copy");
+        return fail(WM_ENOMEM, "request state copy or schedule");
     }
     r->lead = lead_hours;
-    r->sched.resize(greedy_schedule(lead_hours, nullptr, 0));
     greedy_schedule(lead_hours, r->sched.data(), (int)r->sched.size());
     {
         std::lock_guard<std::mutex> lk(s->mu);
