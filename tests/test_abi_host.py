@@ -93,3 +93,32 @@ def test_serve_validation_without_gpu(wm):
     rid = ctypes.c_uint64()
     assert L.wm_serve_submit(None, None, 6, ctypes.byref(rid)) == einval
     assert L.wm_serve_poll(None, 1, None, None) == einval
+
+
+def test_missing_library_raises_no_fallback(wm, monkeypatch, tmp_path):
+    """With the shared library absent every call raises: there is no CPU path."""
+    monkeypatch.setattr(wm, "_LIB", None)
+    monkeypatch.setattr(wm, "LIB_PATH", str(tmp_path / "libwm.so"))
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        wm.lib()
+    with pytest.raises(ImportError):
+        wm.wm_schedule(6)
+
+
+def test_traffic_hash_covers_kernel_sources(tmp_path):
+    """The counter file goes stale on any kernel or launch source change, not on the server's."""
+    import shutil
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src = os.path.join(ROOT, "paper_2503_22235_amd", "csrc")
+    d = tmp_path / "csrc"
+    shutil.copytree(src, d)
+    h0 = bench.kernel_source_hash(str(d))
+    assert h0 == bench.kernel_source_hash()
+    with open(d / "serve.cpp", "a") as f:
+        f.write("\n// host-only edit\n")
+    assert bench.kernel_source_hash(str(d)) == h0
+    with open(d / "k_nat_tile.hip", "a") as f:
+        f.write("\n// kernel edit\n")
+    assert bench.kernel_source_hash(str(d)) != h0
