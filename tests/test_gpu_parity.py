@@ -95,7 +95,10 @@ def test_layernorm(env, prec):
 def test_linear(env, prec, epi):
     wm, torch, ctx = env
     r = np.random.default_rng(2 + epi)
-    for M, N, K in ((1000, 384, 128), (129, 128, 512), (64, 2048, 512), (300, 64, 64)):
+    # N = 512 walks row blocks in pairs: 6 row blocks with a 1-row tail, and
+    # an odd count (3) whose last workgroup has a single, ragged tile
+    for M, N, K in ((1000, 384, 128), (129, 128, 512), (64, 2048, 512), (300, 64, 64),
+                    (1281, 512, 512), (700, 512, 2048)):
         say("linear", prec, epi, M, N, K)
         a = r.standard_normal((M, K)).astype(np.float32)
         w = (r.standard_normal((N, K)) / np.sqrt(K)).astype(np.float32)
