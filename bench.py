@@ -232,20 +232,24 @@ def _counter_rows(d, counter):
 
 def _per_kind(rows):
     """Sum a counter per block-kernel launch, launches identified by their
-    order inside a block: LN, GEMM, attention (bias prep + tile kernel), GEMM,
-    LN, GEMM, GEMM."""
+    order inside a block: LN, GEMM, attention, GEMM, LN, GEMM, GEMM.  A bias
+    table preparation counts with the attention launch that follows it; one
+    followed by anything else (a processor's tables, prepared at creation) is
+    not part of a block."""
     want = {"ln1": "ln", "qkv": "gemm", "nat": "nat", "proj": "gemm", "ln2": "ln", "mlp1": "gemm", "mlp2": "gemm"}
     launches = []
+    prep = None
     for _, name, v in rows:
         if "wm::" not in name:
+            continue
+        if "bias_prep" in name:
+            prep = v
             continue
         t = "ln" if "layernorm" in name else "gemm" if "gemm" in name else "nat" if "nat" in name else None
         if t is None:
             raise SystemExit(f"unexpected library kernel {name}")
-        if t == "nat" and launches and launches[-1][0] == "nat" and "bias_prep" not in name:
-            launches[-1][1] += v
-        else:
-            launches.append([t, v])
+        launches.append([t, v + (prep if t == "nat" and prep is not None else 0.0)])
+        prep = None
     if len(launches) % 7:
         raise SystemExit(f"{len(launches)} launches is not a whole number of blocks")
     acc = {k: [] for k in KIND_ORDER}

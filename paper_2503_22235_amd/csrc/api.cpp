@@ -300,7 +300,9 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
     const size_t nvec = 2 * C + 3 * C + nrpb + C + 2 * C + F + C;
     const size_t nw_bytes = ((size_t)3 * C * C + (size_t)F * C * 2) * esz_big + (size_t)C * C * esz + 4 * 256;
     auto align = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t blk_bytes = align(nvec * 4) + align(nw_bytes) + 4 * 256;
+    // BF16: room for the tiled attention kernel's prepared bias table
+    const size_t tbl_bytes = prec == WM_BF16 ? align((size_t)H * NAT_TBL_WS_FLOATS * 4) : 0;
+    const size_t blk_bytes = align(nvec * 4) + align(nw_bytes) + 4 * 256 + tbl_bytes;
     p->bytes = blk_bytes * n_blocks;
     if ((e = hipMalloc(&p->mem, p->bytes)) != hipSuccess) {
         delete p;
@@ -384,6 +386,29 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
             delete p;
             return hip_fail(e, "weight upload");
         }
+        if (tbl_bytes) {
+            // the table depends on the weights only: prepare it once here
+            // (same arguments as the block's attention launch)
+            NatArgs na{};
+            na.rpb = bw.rpb_log2;
+            na.qscale = 1.0f;
+            na.bscale = 1.0f;
+            na.H = H;
+            na.Kz = g->Kz; na.Ky = g->Ky; na.Kx = g->Kx;
+            na.tbl_ws = (float *)(dev + blk_bytes - tbl_bytes);
+            e = launch_nat_bias_table(na, nullptr);
+            if (e == hipSuccess) bw.nat_tbl = na.tbl_ws;
+            else if (e != hipErrorNotSupported) {   // not supported: a window without a tiled kernel
+                (void)hipFree(p->mem);
+                delete p;
+                return hip_fail(e, "attention bias table");
+            }
+        }
+    }
+    if (tbl_bytes && (e = hipStreamSynchronize(nullptr)) != hipSuccess) {
+        (void)hipFree(p->mem);
+        delete p;
+        return hip_fail(e, "attention bias table");
     }
     *out = p;
     return WM_OK;

@@ -11,7 +11,8 @@
 // footprint at ~66 KB so two workgroups share a CU and one's loads overlap
 // the other's math.  Each wave owns two groups with the same level/lat
 // window pattern, so they share the relative-position-bias lookups, which
-// come from a per-head table prepared once per launch (nat_bias_prep).
+// come from a per-head table (nat_bias_prep): prepared once per processor
+// block when the processor is created, else once per launch.
 //
 // Per group the halo is walked in chunks of 32 keys = 4 lat rows x 8 lon
 // columns at one level.  A chunk costs 5 MFMA:
@@ -824,7 +825,7 @@ hipError_t launch_tile_q(const NatArgs &a, hipStream_t stream) {
         attr_set = true;
     }
     constexpr int TBLP = tbl_padded<KZ, KY, KX>();
-    nat_bias_prep<KZ, KY, KX, QSCALED><<<(a.H * TBLP + 255) / 256, 256, 0, stream>>>(a);
+    if (!a.tbl_ready) nat_bias_prep<KZ, KY, KX, QSCALED><<<(a.H * TBLP + 255) / 256, 256, 0, stream>>>(a);
     const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
     const long total = (long)ntiles * a.H * a.B;
     const unsigned grid = (unsigned)(((total + 7) >> 3) << 3);
@@ -885,6 +886,21 @@ size_t nat_tile_lds_bytes(const NatArgs &a) {
     }
     const int zw = max_halo(a.Z, a.Kz, TZ), yr = std::max(max_halo(a.Y, a.Ky, TY), YR_MIN);
     return a.amax ? tile_lds_fp8(a.Kz, a.Ky, zw, yr) : tile_lds(a.Kz, a.Ky, zw, yr);
+}
+
+template <int KZ, int KY, int KX>
+hipError_t bias_table_only(const NatArgs &a, hipStream_t stream) {
+    constexpr int TBLP = tbl_padded<KZ, KY, KX>();
+    nat_bias_prep<KZ, KY, KX, true><<<(a.H * TBLP + 255) / 256, 256, 0, stream>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_nat_bias_table(const NatArgs &a, hipStream_t stream) {
+    if (a.qscale != 1.0f || a.bscale != 1.0f || !a.tbl_ws || a.H < 1) return hipErrorInvalidValue;
+    if (a.Kz == 5 && a.Ky == 7 && a.Kx == 7) return bias_table_only<5, 7, 7>(a, stream);
+    if (a.Kz == 3 && a.Ky == 5 && a.Kx == 5) return bias_table_only<3, 5, 5>(a, stream);
+    if (a.Kz == 3 && a.Ky == 3 && a.Kx == 3) return bias_table_only<3, 3, 3>(a, stream);
+    return hipErrorNotSupported;
 }
 
 hipError_t launch_nat_tile(const NatArgs &a, hipStream_t stream) {

@@ -129,6 +129,8 @@ struct NatArgs {
     unsigned periodic;
     float *tbl_ws;          // device scratch of NAT_TBL_WS_FLOATS * H floats (tiled kernel;
                             // B * H tables for the FP8 variant)
+    int tbl_ready;          // bf16 tiled kernel: tbl_ws already holds the prepared
+                            // table (see launch_nat_bias_table), skip its preparation
     // FP8 attention: per-state amax of q, k, v (floats at amax[b*amax_stride
     // + 0, 1, 2]); when set and the tiled kernel applies, both contractions
     // run on e4m3 codes with the scales amax/448.
@@ -138,6 +140,11 @@ struct NatArgs {
 constexpr int NAT_TBL_WS_FLOATS = 2048;     // per head, >= padded bias table
 // Picks the LDS-tiled bf16 kernel when it applies, else the generic one.
 hipError_t launch_nat(const NatArgs &a, bool bf16, hipStream_t stream);
+// Writes the tiled bf16 kernel's bias table for a.rpb (already in log2
+// units, q pre-scaled: qscale = bscale = 1) to a.tbl_ws, so that launches
+// with tbl_ready set skip its preparation.  hipErrorNotSupported for windows
+// the tiled kernel does not cover.
+hipError_t launch_nat_bias_table(const NatArgs &a, hipStream_t stream);
 hipError_t launch_nat_generic(const NatArgs &a, bool bf16, hipStream_t stream);
 // LDS bytes of the tiled bf16 kernel for these arguments (0: not applicable).
 size_t nat_tile_lds_bytes(const NatArgs &a);

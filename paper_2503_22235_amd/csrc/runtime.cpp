@@ -115,7 +115,8 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     na.bscale = 1.0f;
     na.B = B; na.Z = g.Z; na.Y = g.Y; na.X = g.X; na.H = H;
     na.Kz = g.Kz; na.Ky = g.Ky; na.Kx = g.Kx; na.periodic = g.periodic_mask;
-    na.tbl_ws = tbl_ws;
+    na.tbl_ws = w.nat_tbl ? w.nat_tbl : tbl_ws;
+    na.tbl_ready = w.nat_tbl != nullptr;
     WM_TIMED(PK_NA, launch_nat(na, bf, s), "NA")
 
     EpiArgs er{};

@@ -18,6 +18,9 @@ struct BlockWeights {
     // FP8 processors: w_qkv, w_1, w_2 hold e4m3 codes with these per-tensor
     // dequantization scales (amax / 448); w_o stays bfloat16.
     float dq_qkv = 1.f, dq_1 = 1.f, dq_2 = 1.f;
+    // BF16 processors: the tiled attention kernel's bias table of this
+    // block, prepared once at creation (null: prepared per launch)
+    float *nat_tbl = nullptr;
 };
 
 constexpr int MAX_BLOCKS = 64;
