@@ -168,11 +168,14 @@ int wm_linear_fp8(int M, int N, int K, const void *a8, float a_dequant,
  * Linear maps are [in][out] (y = x W + b); QKV columns are [Q | K | V].
  * The library copies and converts what it needs (the host array may be
  * freed on return) and owns the device copy until wm_processor_destroy.
- * Requires d = C/heads = 32 and C a multiple of 128.
+ * Requires d = C/heads = 32 and C in {128, 256, 512, 1024}.
  * WM_FP8_E4M3 processors store the QKV and MLP matrices as e4m3 with
- * per-tensor scales (amax / 448) and quantize the LayerNorm outputs and the
- * GELU output per state and per tensor (dynamic amax / 448); attention and
- * the output projection run in bfloat16. */
+ * per-tensor scales (amax / 448) and quantize the LayerNorm outputs, the
+ * GELU output and q, k, v per state and per tensor (dynamic amax / 448);
+ * the attention's QK and PV products run on those e4m3 codes and the output
+ * projection runs in bfloat16.  BF16 processors also prepare each block's
+ * attention bias table on the device here.  Returns once the upload (and
+ * that preparation) has completed on the device. */
 int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks,
                         int mlp_ratio, wm_precision prec,
                         const float *host_params, wm_processor **out);
