@@ -250,13 +250,16 @@ typedef struct {
 int wm_serve_create(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
                     const wm_serve_cfg *cfg, wm_server **out);
 /* Queue a forecast of lead_hours >= 0 from HOST float32 x0 [Z][Y][X][C];
- * x0 is copied before return.  Never waits for the GPU. */
+ * x0 is copied before return.  Never waits for the GPU.  WM_ENOMEM if the
+ * host copy or the request's schedule cannot be allocated. */
 int wm_serve_submit(wm_server *s, const float *x0_host, int lead_hours,
                     uint64_t *id_out);
 /* WM_OK: request id finished; its state is copied to HOST out_host (float32
  * [Z][Y][X][C], may be NULL) and stats to *st (may be NULL), and the request
  * is forgotten.  WM_EAGAIN: still queued or running.  WM_ENOTFOUND: unknown
- * (or already collected) id.  Never waits for the GPU. */
+ * (or already collected) id.  After a failure inside the scheduler (a HIP
+ * error, or WM_ENOMEM for a host allocation) every poll returns that code
+ * and the server does no further work.  Never waits for the GPU. */
 int wm_serve_poll(wm_server *s, uint64_t id, float *out_host, wm_req_stats *st);
 /* Counters: queued, admitted-and-running, finished-not-collected, slots. */
 int wm_serve_status(wm_server *s, int *queued, int *running, int *done, int *slots);
