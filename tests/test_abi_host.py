@@ -122,3 +122,22 @@ def test_traffic_hash_covers_kernel_sources(tmp_path):
     with open(d / "k_nat_tile.hip", "a") as f:
         f.write("\n// kernel edit\n")
     assert bench.kernel_source_hash(str(d)) != h0
+
+
+def test_counter_attribution_per_block_kernel():
+    """rocprofv3 counter rows are attributed to the block's kernels by launch
+    order; a bias-table preparation joins the attention launch after it, and
+    tables prepared at processor creation (not followed by an attention
+    launch) are left out."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    ns = "wm::(anonymous namespace)::"
+    block = [(ns + "layernorm_kernel", 1.0), (ns + "gemm_lds_kernel", 2.0),
+             (ns + "nat_bias_prep", 0.5), (ns + "nat_tile_kernel", 3.0), (ns + "gemm_lds_kernel", 4.0),
+             (ns + "layernorm_kernel", 5.0), (ns + "gemm_lds_kernel", 6.0), (ns + "gemm_lds_kernel", 7.0)]
+    cached = [b for b in block if "bias_prep" not in b[0]]
+    rows = [(ns + "nat_bias_prep", 100.0)] * 3 + [("at::neg_kernel", 9.0)] + block + cached
+    rows = [(i, n, v) for i, (n, v) in enumerate(rows)]
+    got = bench._per_kind(rows)
+    assert got == {"ln1": 1.0, "qkv": 2.0, "nat": 3.25, "proj": 4.0, "ln2": 5.0, "mlp1": 6.0, "mlp2": 7.0}
