@@ -456,19 +456,21 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
     constexpr size_t lds = (size_t)STAGES * (BM + BN) * BKB;
     static_assert(lds * OCC <= 160 * 1024, "LDS per CU");
     constexpr int NTH = 64 * WGM * WGN;
-    static bool attr_set = false;
-    if (!attr_set) {
+    // LDS limit of the variants, set once per process (a local static's
+    // initialisation is thread-safe; the server thread launches too)
+    static const hipError_t attr_err = [] {
         const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8>};
         for (const void *f : fns) {
-            hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
-        attr_set = true;
-    }
+        return hipSuccess;
+    }();
+    if (attr_err != hipSuccess) return attr_err;
     const int ntn = N / BN;
     // Output-feature tiles per workgroup (WM_GEMM_TPW overrides, for tuning).
     static const int tpw_env = [] {

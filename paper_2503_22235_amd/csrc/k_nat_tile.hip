@@ -817,13 +817,10 @@ template <int KZ, int KY, int KX, bool QSCALED>
 hipError_t launch_tile_q(const NatArgs &a, hipStream_t stream) {
     const int zw = max_halo(a.Z, KZ, TZ), yr = std::max(max_halo(a.Y, KY, TY), YR_MIN);
     const size_t lds = tile_lds(KZ, KY, zw, yr);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)nat_tile_kernel<KZ, KY, KX, QSCALED>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // set once per process (thread-safe local static initialisation)
+    static const hipError_t attr_err = hipFuncSetAttribute((const void *)nat_tile_kernel<KZ, KY, KX, QSCALED>,
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr_err != hipSuccess) return attr_err;
     constexpr int TBLP = tbl_padded<KZ, KY, KX>();
     if (!a.tbl_ready) nat_bias_prep<KZ, KY, KX, QSCALED><<<(a.H * TBLP + 255) / 256, 256, 0, stream>>>(a);
     const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
@@ -842,13 +839,10 @@ template <int KZ, int KY, int KX>
 hipError_t launch_tile_fp8(const NatArgs &a, hipStream_t stream) {
     const int zw = max_halo(a.Z, KZ, TZ), yr = std::max(max_halo(a.Y, KY, TY), YR_MIN);
     const size_t lds = tile_lds_fp8(KZ, KY, zw, yr);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)nat_tile_fp8_kernel<KZ, KY, KX>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // set once per process (thread-safe local static initialisation)
+    static const hipError_t attr_err = hipFuncSetAttribute((const void *)nat_tile_fp8_kernel<KZ, KY, KX>,
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr_err != hipSuccess) return attr_err;
     constexpr int TBLP = tbl_padded<KZ, KY, KX>();
     nat_bias_prep_fp8<KZ, KY, KX><<<(a.B * a.H * TBLP + 255) / 256, 256, 0, stream>>>(a);
     const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
