@@ -76,7 +76,11 @@ const char *wm_version(void);
 
 /* Context bound to one HIP device.  It owns a workspace that grows on
  * demand to hold a block's intermediates for the largest batch seen.
- * The caller destroys it after all work enqueued through it has finished. */
+ * The caller destroys it after all work enqueued through it has finished.
+ * A context serves one thread (and one stream) at a time: work enqueued
+ * through it on two streams at once would share its workspace.  Processors
+ * are read-only after creation and may be shared by any number of
+ * contexts and threads. */
 int wm_ctx_create(int device, wm_ctx **out);
 void wm_ctx_destroy(wm_ctx *ctx);
 
