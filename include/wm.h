@@ -78,9 +78,9 @@ const char *wm_version(void);
  * demand to hold a block's intermediates for the largest batch seen.
  * The caller destroys it after all work enqueued through it has finished.
  * A context serves one thread (and one stream) at a time: work enqueued
- * through it on two streams at once would share its workspace.  Processors
- * are read-only after creation and may be shared by any number of
- * contexts and threads. */
+ * through it on two streams at once would share its workspace.  A
+ * processor is only read by the calls that run it (wm_processor_set_rope
+ * aside), so any number of contexts and threads may run it at once. */
 int wm_ctx_create(int device, wm_ctx **out);
 void wm_ctx_destroy(wm_ctx *ctx);
 
