@@ -570,8 +570,11 @@ hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, Ep
         const char *v = getenv("WM_GEMM_CFG");
         return v ? atoi(v) : -1;
     }();
-    if (N % 256 == 0 && cfg != 0)
-        return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, wide_tpw(N));
+    if (N % 256 == 0 && cfg != 0) {
+        // N = 512 (MLP2 at C = 512): row walk, as in launch_gemm_lds
+        if (N == 512) return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, 2, 1);
+        return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, wide_tpw(N), 0);
+    }
     return launch_cfg<128, 128, 128, 2, 2, 2, 2, true>(A, W, M, N, K, epi, ep, stream);
 }
 
