@@ -121,8 +121,11 @@ def time_steps(wm, torch, ctx, proc, x, B, steps, warmup, profile=False):
     return dt, prof
 
 
-def serve_run(wm, np, S, ctx, g, p6, p1, n_req, rate, max_batch, seed=3):
-    """Poisson arrivals, leads uniform in 1..336 h, BF16 states in HBM slots."""
+def serve_run(wm, np, S, ctx, g, p6, p1, n_req, rate, max_batch, seed=3, cap_s=240.0):
+    """Poisson arrivals, leads uniform in 1..336 h, BF16 states in HBM slots.
+
+    Requests whose arrival time falls after cap_s seconds are not submitted
+    (the run reports how many were submitted and completed)."""
     import wm_synth
     arrivals, leads = wm_synth.serving_trace(n_req, rate, seed=seed)
     x0 = S.latent_state(g, 1, seed=0)[0]
@@ -135,13 +138,14 @@ def serve_run(wm, np, S, ctx, g, p6, p1, n_req, rate, max_batch, seed=3):
     t0 = time.perf_counter()
     nxt = 0
     t_log = 0.0
-    while nxt < n_req or pending:
+    n_sub = int(np.searchsorted(arrivals, cap_s, side="right"))
+    while nxt < n_sub or pending:
         now = time.perf_counter() - t0
         if now - t_log > 20.0:
             t_log = now
-            print(f"bench: serving {now:.0f} s: {len(stats)}/{n_req} done, {len(pending)} in flight",
+            print(f"bench: serving {now:.0f} s: {len(stats)}/{n_sub} done, {len(pending)} in flight",
                   file=sys.stderr, flush=True)
-        while nxt < n_req and arrivals[nxt] <= now:
+        while nxt < n_sub and arrivals[nxt] <= now:
             rid = wm.wm_serve_submit(srv, x0, int(leads[nxt]))
             pending[rid] = nxt
             nxt += 1
@@ -155,13 +159,15 @@ def serve_run(wm, np, S, ctx, g, p6, p1, n_req, rate, max_batch, seed=3):
     lat = np.array([s["t_done"] - s["t_submit"] for s in stats])
     steps = sum(s["steps"] for s in stats)
     span = max(s["t_done"] for s in stats) - min(s["t_submit"] for s in stats)
-    batches = sum(s["batches"] for s in stats)
-    return {"requests": n_req, "rate_per_s": round(rate, 3), "max_batch": max_batch, "slots": slots,
+    cob = np.array([s["max_cobatch"] for s in stats if s["steps"] > 0])
+    return {"requests": n_req, "requests_submitted": n_sub, "requests_completed": len(stats),
+            "arrival_cap_s": cap_s, "rate_per_s": round(rate, 3), "max_batch": max_batch, "slots": slots,
             "leads_h": "uniform 1..336", "state": "bf16 in HBM",
-            "steps_per_s": round(steps / span, 2), "requests_per_s": round(n_req / span, 3),
+            "steps_per_s": round(steps / span, 2), "requests_per_s": round(len(stats) / span, 3),
             "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
-            "mean_steps": round(steps / n_req, 2), "arrivals": arrivals, "leads": leads,
-            "_batches": batches}
+            "mean_steps": round(steps / len(stats), 2),
+            "requests_cobatched": int((cob >= 2).sum()), "max_cobatch": int(cob.max()) if cob.size else 0,
+            "arrivals": arrivals[:n_sub], "leads": leads[:n_sub]}
 
 
 def fifo_model(wm, arrivals, leads, step_s):
@@ -175,7 +181,7 @@ def fifo_model(wm, arrivals, leads, step_s):
         lat.append(free - a)
     lat = np.array(lat)
     return {"p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
-            "kind": "FIFO replay of the same arrivals at the measured FP32 step time"}
+            "kind": "model, not a served run: FIFO replay of the same arrivals at the measured FP32 step time"}
 
 
 def cpu_baseline(g, params, nblocks=2):
@@ -207,9 +213,23 @@ def cpu_baseline(g, params, nblocks=2):
         O.block(x1, S.split_block_params(g1, p1, 0), g1)
         dt1 = time.perf_counter() - t1
     return {"value": round(1.0 / (8 * dt), 5), "unit": "processor-steps/s", "cores": threads, "kind": "oracle",
+            "host": host_cpu(),
             "sample": f"{nblocks} of the 8 blocks of one step on the full 8x90x180 grid, FP64 "
                       f"({dt:.1f} s per block); steps/s = 1/(8 x block time)",
             "small_block_single_thread_s": round(dt1, 3)}
+
+
+def host_cpu():
+    """CPUs this process may run on, CPUs online and the CPU model name."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "online": os.cpu_count(), "model": model}
 
 
 KIND_ORDER = ("ln1", "qkv", "nat", "proj", "ln2", "mlp1", "mlp2")
@@ -305,7 +325,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serve-cap-s", type=float, default=240.0,
+                    help="submit only the requests that arrive within this many seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-fp8", action="store_true")
@@ -457,7 +479,8 @@ def main():
     if not args.no_serve and args.serve_requests > 0:
         rate = 0.7 * sps / 30.17
         log(f"serving run: {args.serve_requests} requests at {rate:.2f}/s")
-        sv = serve_run(wm, np, S, ctx, g, p_bf, p1_bf, args.serve_requests, rate, max_batch=8)
+        sv = serve_run(wm, np, S, ctx, g, p_bf, p1_bf, args.serve_requests, rate, max_batch=8,
+                       cap_s=args.serve_cap_s)
         out["serve"] = {k: v for k, v in sv.items() if not k.startswith("_") and k not in ("arrivals", "leads")}
         out["_serve_trace"] = (sv["arrivals"], sv["leads"])
     p1_bf.close()
@@ -497,7 +520,13 @@ def main():
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, params6)
     ctx.close()
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
+    sys.stderr.flush()
+    # Every child process this run started has been waited for and every
+    # server thread joined; end here without the interpreter's teardown of
+    # the HIP runtime and its allocations, which can outlast the output.
+    os._exit(0)
 
 
 if __name__ == "__main__":

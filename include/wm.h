@@ -177,7 +177,10 @@ int wm_linear_fp8(int M, int N, int K, const void *a8, float a_dequant,
  * per-tensor scales (amax / 448) and quantize the LayerNorm outputs, the
  * GELU output and q, k, v per state and per tensor (dynamic amax / 448);
  * the attention's QK and PV products run on those e4m3 codes and the output
- * projection runs in bfloat16.  BF16 processors also prepare each block's
+ * projection runs in bfloat16.  The e4m3 attention exists for a lon-periodic
+ * grid (periodic_mask 4), a 5x7x7, 3x5x5 or 3x3x3 window and X >= Kx + 7;
+ * an FP8 processor on any other grid is rejected with WM_EINVAL (checked
+ * before the context, so no device is needed to be told).  BF16 processors also prepare each block's
  * attention bias table on the device here.  Returns once the upload (and
  * that preparation) has completed on the device. */
 int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks,
@@ -197,7 +200,11 @@ int wm_processor_set_rope(wm_processor *p, int on);
 
 int wm_processor_blocks(const wm_processor *p);
 
-/* One block, in place on x (device float32 [B][Z][Y][X][C]):
+/* One block of the processor (Sec. 2.1 "Encoder-processor-decoder
+ * architecture" and "NATTEN": a transformer block of 3-D neighborhood
+ * attention on the latent grid; App. A.2 for the window and its borders;
+ * the pre-norm layout, biases and GELU are this library's reading where
+ * the paper is silent), in place on x (device float32 [B][Z][Y][X][C]):
  *   x1 = x + NA(LN1(x) W_qkv + b_qkv) W_o + b_o
  *   x  = x1 + GELU(LN2(x1) W_1 + b_1) W_2 + b_2
  * LayerNorm statistics, softmax max/sum and the residual stream are
@@ -216,8 +223,10 @@ int wm_processor_step(wm_ctx *ctx, const wm_processor *p, int B, float *x,
  * number of steps.  Negative lead or too small cap -> WM_EINVAL. */
 int wm_schedule(int lead_hours, int *steps_out, int cap);
 
-/* Latent rollout: run the six-hour processor p6 and the one-hour processor
- * p1 on x in place following wm_schedule(lead_hours), with no host
+/* Latent rollout (Sec. 2.1: the six-hour and one-hour processors are
+ * applied in latent space, chosen by a greedy schedule, until the lead time
+ * is reached): run the six-hour processor p6 and the one-hour processor p1
+ * on x in place following wm_schedule(lead_hours), with no host
  * synchronisation between steps.  Lead 0 leaves x unchanged. */
 int wm_rollout(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
                int B, float *x, int lead_hours, void *stream);
@@ -247,6 +256,7 @@ typedef struct {
     int steps;                 /* processor steps the request ran                  */
     int batches;               /* step launches it was part of                     */
     double t_submit, t_admit, t_done;   /* seconds on the steady clock            */
+    int max_cobatch;           /* most requests in one step launch it was part of  */
 } wm_req_stats;
 
 /* p6, p1 must share one grid and stay alive until wm_serve_destroy.  The

@@ -41,7 +41,8 @@ class wm_serve_cfg(ctypes.Structure):
 class wm_req_stats(ctypes.Structure):
     _fields_ = [("id", ctypes.c_uint64), ("lead_hours", ctypes.c_int), ("steps", ctypes.c_int),
                 ("batches", ctypes.c_int), ("t_submit", ctypes.c_double),
-                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("max_cobatch", ctypes.c_int)]
 
 
 class wm_grid(ctypes.Structure):

@@ -52,6 +52,22 @@ int validate_grid(const wm_grid *g, bool need_block) {
     return WM_OK;
 }
 
+// Whether the e4m3 attention kernel covers grid g at batch B with token
+// stride ts (elements) (the FP8 processors and wm_nat_forward in FP8 have no
+// other attention kernel).
+bool fp8_attention_applies(const wm_grid *g, int B, long ts) {
+    static float dummy_tbl;
+    static float dummy_amax;
+    NatArgs a{};
+    a.ts = ts;
+    a.B = B; a.Z = g->Z; a.Y = g->Y; a.X = g->X; a.H = g->heads;
+    a.Kz = g->Kz; a.Ky = g->Ky; a.Kx = g->Kx; a.periodic = g->periodic_mask;
+    a.tbl_ws = &dummy_tbl;       // only tested for null
+    a.amax = &dummy_amax;
+    const size_t lds = nat_tile_lds_bytes(a);
+    return lds > 0 && lds <= 160 * 1024;
+}
+
 int ctx_reserve(wm_ctx *ctx, size_t bytes) {
     if (bytes <= ctx->ws_bytes) return WM_OK;
     hipError_t e;
@@ -192,7 +208,7 @@ int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec, cons
     hipStream_t s = (hipStream_t)stream;
     hipError_t e;
     if (fp8) {
-        if (nat_tile_lds_bytes(a) == 0)   // a.amax is still null: asks whether the tiled kernels apply
+        if (!fp8_attention_applies(g, B, g->C))
             return fail(WM_EINVAL, "FP8 attention needs lon-periodic only, a 5x7x7, 3x5x5 or 3x3x3 window "
                                    "and lon >= 8 + Kx - 1");
         unsigned *amax = (unsigned *)((char *)ctx->ws + tbl_bytes);
@@ -271,14 +287,19 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
                         const float *host_params, wm_processor **out) {
     if (!out) return fail(WM_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
+    // Argument checks come before the context's: they need no device.
     int rc = validate_grid(g, true);
     if (rc) return rc;
     if (n_blocks < 1 || n_blocks > 64) return fail(WM_EINVAL, "n_blocks must be 1..64");
     if (mlp_ratio < 1 || mlp_ratio > 8) return fail(WM_EINVAL, "mlp_ratio must be 1..8");
     if (prec != WM_F32 && prec != WM_BF16 && prec != WM_FP8_E4M3)
         return fail(WM_EINVAL, "processor precision %d not supported", (int)prec);
+    // (head-major q, k, v: 32 elements per token)
+    if (prec == WM_FP8_E4M3 && !fp8_attention_applies(g, 1, 32))
+        return fail(WM_EINVAL, "FP8 processors run QK and PV on e4m3 codes, which needs lon-periodic only "
+                               "(periodic_mask 4), a 5x7x7, 3x5x5 or 3x3x3 window and lon >= 8 + Kx - 1");
     if (!host_params) return fail(WM_EINVAL, "host_params is NULL");
+    if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
 

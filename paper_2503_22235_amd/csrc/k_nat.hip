@@ -239,6 +239,9 @@ hipError_t launch_nat(const NatArgs &a, bool bf16in, hipStream_t stream) {
         const size_t lds = nat_tile_lds_bytes(a);
         if (lds > 0 && lds <= 160 * 1024) return launch_nat_tile(a, stream);
     }
+    // e4m3 contractions exist only in the tiled kernel: never fall back to
+    // bf16 arithmetic for a caller that asked for them
+    if (a.amax) return hipErrorNotSupported;
     return launch_nat_generic(a, bf16in, stream);
 }
 

@@ -165,6 +165,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
     if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
     if (B > 64) return fail(WM_EINVAL, "FP8 processors take at most 64 states per call");
+    if (!fp8_attention_applies(&g, B, 32)) return fail(WM_EINVAL, "no e4m3 attention kernel for this grid and batch");
     if ((e = launch_zero_u32(amax, (size_t)AMAX_SHARDS * AMAX_STRIDE, s)) != hipSuccess)
         return hip_fail(e, "amax reset");
     WM_TIMED(PK_LN1, launch_layernorm_fp8(x, w.ln1_g, w.ln1_b, M, C, (int)T, 1e-5f, amax_u, act8, s), "LN1")

@@ -63,6 +63,8 @@ namespace wm {
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int ctx_reserve(wm_ctx *ctx, size_t bytes);
+bool fp8_attention_applies(const wm_grid *g, int B, long ts);
+
 
 // Bytes of workspace a block of processor p needs for B states.
 size_t block_workspace_bytes(const wm_processor *p, int B);

@@ -113,7 +113,15 @@ struct wm_server {
             snprintf(err_msg, sizeof err_msg, "%s: %s", what, hipGetErrorString(e));
         }
     }
-    static bool done(hipEvent_t e) { return hipEventQuery(e) == hipSuccess; }
+    // Whether the work before event e has finished.  Only hipErrorNotReady
+    // means "still running": any other code is an asynchronous failure,
+    // recorded so that every later poll reports it.
+    bool done(hipEvent_t e) {
+        const hipError_t q = hipEventQuery(e);
+        if (q == hipSuccess) return true;
+        if (q != hipErrorNotReady) set_error(WM_EHIP, "device work", q);
+        return false;
+    }
 
     // ---- one scheduler iteration; returns true if it made progress ----
     // Called with `lk` held; host copies of whole states run with it released
@@ -121,6 +129,7 @@ struct wm_server {
     bool step_once(std::unique_lock<std::mutex> &lk) {
         bool progress = false;
         hipError_t e;
+        if (err_code != WM_OK) return false;
         // retire state copies
         Request *finished = nullptr;
         for (auto &kv : reqs) {
@@ -164,6 +173,7 @@ struct wm_server {
                 r->cursor += 1;
                 r->stats.steps += 1;
                 r->stats.batches += 1;
+                r->stats.max_cobatch = std::max(r->stats.max_cobatch, (int)b.reqs.size());
                 r->st = RQ_IDLE;
             }
             put_event(b.ev);

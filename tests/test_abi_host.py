@@ -84,6 +84,36 @@ def wm_status(name):
     return int(m.group(1))
 
 
+def test_fp8_processor_needs_e4m3_attention_without_gpu(wm):
+    """An FP8 processor runs QK and PV on e4m3 codes; on a grid or window the
+    e4m3 attention does not cover it is refused (WM_EINVAL) before any
+    device work -- it never falls back to bf16 attention.  The same grids in
+    BF16 are accepted up to the context check."""
+    import numpy as np
+    L = wm.lib()
+    einval = wm_status("WM_EINVAL")
+    params = np.zeros(16, np.float32)       # never read: the call fails first
+    out = ctypes.c_void_p()
+    uncovered = [
+        wm.wm_grid(8, 90, 180, 512, 16, 3, 5, 7, 4),   # window without an e4m3 kernel
+        wm.wm_grid(8, 90, 180, 512, 16, 5, 7, 7, 0),   # lon not periodic
+        wm.wm_grid(8, 90, 180, 512, 16, 5, 7, 7, 6),   # lat periodic too
+        wm.wm_grid(8, 90, 13, 512, 16, 5, 7, 7, 4),    # lon shorter than the halo (8 + Kx - 1)
+    ]
+    for g in uncovered:
+        assert L.wm_processor_create(None, ctypes.byref(g), 1, 4, 2, params.ctypes.data,
+                                     ctypes.byref(out)) == einval
+        assert b"e4m3" in L.wm_last_error(), L.wm_last_error()
+        # BF16 gets past the grid checks and stops at the missing context
+        assert L.wm_processor_create(None, ctypes.byref(g), 1, 4, 1, params.ctypes.data,
+                                     ctypes.byref(out)) == einval
+        assert b"ctx" in L.wm_last_error()
+    ok = wm.wm_grid(8, 90, 180, 512, 16, 5, 7, 7, 4)
+    assert L.wm_processor_create(None, ctypes.byref(ok), 1, 4, 2, params.ctypes.data,
+                                 ctypes.byref(out)) == einval
+    assert b"ctx" in L.wm_last_error()
+
+
 def test_serve_validation_without_gpu(wm):
     L = wm.lib()
     einval = wm_status("WM_EINVAL")

@@ -48,7 +48,10 @@ def test_quantize_codes_bit_exact(env):
 def test_linear_fp8(env, epi):
     wm, torch, ctx = env
     r = np.random.default_rng(1 + epi)
-    for M, N, K in ((1000, 384, 128), (300, 128, 512), (129, 256, 256)):
+    # N = 512 takes the row walk (two row blocks of one feature tile per
+    # workgroup): 6 row blocks with a 1-row tail, and an odd count (3) whose
+    # last workgroup has a single, ragged tile
+    for M, N, K in ((1000, 384, 128), (300, 128, 512), (129, 256, 256), (1281, 512, 512), (700, 512, 2048)):
         say("linear fp8", epi, M, N, K)
         a8 = O.e4m3_encode(r.standard_normal((M, K)) * 40)
         w8 = O.e4m3_encode(r.standard_normal((N, K)) * 40)
@@ -113,6 +116,7 @@ def test_fp8_blocks_full_size_sampled(env):
         err, inc = O.rel_l2(got, ref), O.rel_l2(got - xs, ref - xs)
         say(f"fp8 block {b} rel_l2={err:.3e} increment={inc:.3e}")
         assert err < 1e-1
+        assert inc < 1e-1
     p.close()
 
 
@@ -159,6 +163,8 @@ FP8_NAT_GRIDS = [
     S.Grid(Z=3, Y=10, X=21, C=128, heads=4, Kz=3, Ky=5, Kx=5, periodic_mask=4),
     S.Grid(Z=8, Y=16, X=24, C=64, heads=2, Kz=5, Ky=7, Kx=7, periodic_mask=4),
     S.Grid(Z=4, Y=9, X=12, C=64, heads=2, Kz=3, Ky=3, Kx=3, periodic_mask=4),
+    # 5x7x7 with ragged query tiles in lat (18 = 4 x 4 + 2) and lon (20 = 2 x 8 + 4)
+    S.Grid(Z=8, Y=18, X=20, C=64, heads=2, Kz=5, Ky=7, Kx=7, periodic_mask=4),
 ]
 
 
@@ -242,3 +248,27 @@ def test_fp8_block_batch_17_row_chunks(env):
     wm.wm_processor_block(ctx, p, 0, 1, x1)
     assert torch.equal(xb[B - 1:B], x1)
     p.close()
+
+
+def test_nat_fp8_full_size_against_quantized_operands(env):
+    """FP8 attention alone at 8 x 90 x 180, 16 heads, window 5x7x7 (ragged
+    query tiles in lat and lon, poles, the lon seam), every output, two
+    states with different per-state scales; reference: the oracle (C loops)
+    on q, k, v quantized by the oracle's e4m3 codec."""
+    wm, torch, ctx = env
+    g = S.CFG2
+    B = 2
+    r = np.random.default_rng(60)
+    shape = (B, g.T, g.heads, 32)
+    q = _bf16(torch, r.standard_normal(shape) * np.array([1.0, 3.0])[:, None, None, None])
+    k = _bf16(torch, r.standard_normal(shape) * np.array([1.0, 2.0])[:, None, None, None])
+    v = _bf16(torch, r.standard_normal(shape))
+    rpb = r.standard_normal(g.rpb_shape).astype(np.float32).astype(np.float64)
+    say("fp8 nat full size")
+    got = _nat_fp8(env, g, q, k, v, rpb)
+    for b in range(B):
+        quant = O.nat_c(_q8(q[b], np.abs(q[b]).max()), _q8(k[b], np.abs(k[b]).max()),
+                        _q8(v[b], np.abs(v[b]).max()), rpb, g)
+        e_q = O.rel_l2(got[b], quant)
+        say(f"fp8 nat 8x90x180 state {b}: vs quantized-operand reference {e_q:.4f}")
+        assert e_q < 0.04

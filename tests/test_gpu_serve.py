@@ -65,8 +65,13 @@ def test_serve_alone_equals_mix(env, prec, bf16_state):
         assert np.array_equal(r[rid], res_mix[ids[i]]), f"request {i} differs alone vs in the mix"
         assert st[rid]["steps"] == len(O.schedule(lead))
     alone.close()
-    batched = sum(1 for s in st_mix.values() if s["steps"] > 0)
-    assert batched > 0
+    # continuous batching: twelve requests submitted at once with four
+    # admitted slots per batch -- some step launch held two or more of them
+    cob = max(s["max_cobatch"] for s in st_mix.values())
+    say("serve mix: most requests in one step launch", cob)
+    assert cob >= 2
+    for s in st_mix.values():
+        assert s["max_cobatch"] <= 4 and (s["steps"] == 0) == (s["max_cobatch"] == 0)
     for i, rid in enumerate(ids):
         s = st_mix[rid]
         assert s["t_submit"] <= s["t_admit"] <= s["t_done"]
