@@ -128,6 +128,24 @@ int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec,
                    const void *q, const void *k, const void *v,
                    const float *rpb, void *out, void *stream);
 
+/* wm_nat_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, layouts, results and errors as wm_nat_forward, without a
+ * context.  It runs on the calling thread's current HIP device, and
+ * `stream` must belong to that device.  Its scratch (bias tables, FP8 amax
+ * slots) is one fixed array of WM_NAT_NOALLOC_SCRATCH_BYTES in each
+ * device's memory, held from the first call on that device until the
+ * process ends; it calls no hipMalloc/hipFree.  Calls needing more scratch
+ * than that -- heads * 8 KiB for F32/BF16, B * heads * 8 KiB + 128 KiB for
+ * WM_FP8_E4M3 -- return WM_EINVAL.  Every call on one device shares that
+ * array and rewrites what it reads before reading it, so calls whose work
+ * overlaps on one device (two streams, or two threads) race: serialize
+ * them. */
+#define WM_NAT_NOALLOC_SCRATCH_BYTES (4u << 20)
+int wm_nat_forward_noalloc(const wm_grid *g, int B, wm_precision prec,
+                           const void *q, const void *k, const void *v,
+                           const float *rpb, void *out, void *stream);
+
 /* LayerNorm of M rows of C float32 values, float32 statistics with biased
  * variance (the block's two norms; the pre-norm vision-transformer layout
  * the paper builds on, Sec. 2.1):

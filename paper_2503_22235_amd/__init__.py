@@ -20,10 +20,11 @@ __all__ = [
     "wm_schedule", "wm_rollout", "wm_forecast_hourly", "wm_relerr_l2", "grid_of", "LIB_PATH",
     "wm_prof_enable", "wm_prof_select", "wm_prof_collect", "PROF_KINDS", "wm_serve_create",
     "wm_serve_submit", "wm_serve_poll", "wm_serve_status", "wm_serve_destroy",
-    "wm_quantize_fp8", "wm_linear_fp8",
+    "wm_quantize_fp8", "wm_linear_fp8", "wm_nat_forward_noalloc", "WM_NAT_NOALLOC_SCRATCH_BYTES",
 ]
 
 WM_F32, WM_BF16, WM_FP8_E4M3 = 0, 1, 2
+WM_NAT_NOALLOC_SCRATCH_BYTES = 4 << 20   # the fixed per-device scratch of wm_nat_forward_noalloc
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwm.so")
 
 
@@ -72,6 +73,7 @@ _SIGS = {
     "wm_ctx_destroy": (None, [_vp]),
     "wm_nat_indices": (_int, [ctypes.POINTER(wm_grid), _vp, _vp]),
     "wm_nat_forward": (_int, [_vp, ctypes.POINTER(wm_grid), _int, _int, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "wm_nat_forward_noalloc": (_int, [ctypes.POINTER(wm_grid), _int, _int, _vp, _vp, _vp, _vp, _vp, _vp]),
     "wm_layernorm": (_int, [_int, _int, _vp, _vp, _vp, ctypes.c_float, _int, _vp, _vp]),
     "wm_linear": (_int, [_int, _int, _int, _int, _vp, _vp, _vp, _int, _vp, _vp]),
     "wm_processor_create": (_int, [_vp, ctypes.POINTER(wm_grid), _int, _int, _int, _vp, ctypes.POINTER(_vp)]),
@@ -198,6 +200,12 @@ def wm_nat_forward(ctx, grid, B, prec, q, k, v, rpb, out, stream=None):
     g = grid_of(grid)
     return _check(lib().wm_nat_forward(ctx.handle, ctypes.byref(g), B, prec, _ptr(q), _ptr(k),
                                        _ptr(v), _ptr(rpb), _ptr(out), _stream(stream)))
+
+
+def wm_nat_forward_noalloc(grid, B, prec, q, k, v, rpb, out, stream=None):
+    g = grid_of(grid)
+    return _check(lib().wm_nat_forward_noalloc(ctypes.byref(g), B, prec, _ptr(q), _ptr(k), _ptr(v),
+                                               _ptr(rpb), _ptr(out), _stream(stream)))
 
 
 def wm_layernorm(M, C, x, gamma, beta, eps, out_prec, out, stream=None):

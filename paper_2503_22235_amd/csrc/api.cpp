@@ -87,6 +87,59 @@ int ctx_reserve(wm_ctx *ctx, size_t bytes) {
     return WM_OK;
 }
 
+
+// Argument checks of the attention entry points; *ws_need receives the
+// scratch bytes nat_forward_into uses (bias tables, FP8 amax slots).
+int nat_forward_check(const wm_grid *g, int B, wm_precision prec, const void *q, const void *k, const void *v,
+                      const float *rpb, void *out, size_t *ws_need) {
+    int rc = validate_grid(g, false);
+    if (rc) return rc;
+    if (B < 0) return fail(WM_EINVAL, "negative batch");
+    if (prec != WM_F32 && prec != WM_BF16 && prec != WM_FP8_E4M3) return fail(WM_EINVAL, "unknown precision");
+    const bool fp8 = prec == WM_FP8_E4M3;
+    if (fp8 && B > 64) return fail(WM_EINVAL, "FP8 attention takes at most 64 states per call");
+    *ws_need = (size_t)(fp8 ? B : 1) * g->heads * NAT_TBL_WS_FLOATS * 4 +
+               (fp8 ? (size_t)AMAX_SHARDS * AMAX_STRIDE * 4 : 0);
+    if (B == 0) return WM_OK;
+    if (!q || !k || !v || !rpb || !out) return fail(WM_EINVAL, "NULL tensor");
+    if (fp8 && !fp8_attention_applies(g, B, g->C))
+        return fail(WM_EINVAL, "FP8 attention needs lon-periodic only, a 5x7x7, 3x5x5 or 3x3x3 window "
+                               "and lon >= 8 + Kx - 1");
+    return WM_OK;
+}
+
+// Enqueue the attention of wm_nat_forward (arguments already checked by
+// nat_forward_check, B > 0) with its scratch at device address ws.
+int nat_forward_into(const wm_grid *g, int B, wm_precision prec, const void *q, const void *k, const void *v,
+                     const float *rpb, void *out, void *ws, hipStream_t s) {
+    const long T = (long)g->Z * g->Y * g->X;
+    const bool fp8 = prec == WM_FP8_E4M3;
+    const size_t tbl_bytes = (size_t)(fp8 ? B : 1) * g->heads * NAT_TBL_WS_FLOATS * 4;
+    NatArgs a{};
+    a.q = q; a.k = k; a.v = v;
+    a.bs = T * g->C; a.ts = g->C; a.hs = 32;
+    a.out = out; a.obs = T * g->C; a.ots = g->C;
+    a.rpb = rpb;
+    a.qscale = LOG2E / std::sqrt(32.0f);
+    a.bscale = LOG2E;
+    a.B = B; a.Z = g->Z; a.Y = g->Y; a.X = g->X; a.H = g->heads;
+    a.Kz = g->Kz; a.Ky = g->Ky; a.Kx = g->Kx; a.periodic = g->periodic_mask;
+    a.tbl_ws = (float *)ws;
+    hipError_t e;
+    if (fp8) {
+        unsigned *amax = (unsigned *)((char *)ws + tbl_bytes);
+        if ((e = launch_zero_u32(amax, (size_t)AMAX_SHARDS * AMAX_STRIDE, s)) != hipSuccess) return hip_fail(e, "zero");
+        const void *src[3] = {q, k, v};
+        for (int i = 0; i < 3; ++i)
+            if ((e = launch_amax_bf16(src[i], (size_t)T * g->C, B, amax + i, 3, s)) != hipSuccess)
+                return hip_fail(e, "amax");
+        if ((e = launch_amax_fold(amax, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
+        a.amax = (const float *)amax;
+        a.amax_stride = 3;
+    }
+    e = launch_nat(a, prec != WM_F32, s);
+    return e == hipSuccess ? WM_OK : hip_fail(e, "nat launch");
+}
 }  // namespace wm
 
 static uint16_t host_bf16(float f) {
@@ -182,47 +235,14 @@ int wm_nat_indices(const wm_grid *g, int *dev_out, void *stream) {
 
 int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec, const void *q, const void *k,
                    const void *v, const float *rpb, void *out, void *stream) {
-    int rc = validate_grid(g, false);
+    size_t need = 0;
+    int rc = nat_forward_check(g, B, prec, q, k, v, rpb, out, &need);
     if (rc) return rc;
     if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
-    if (B < 0) return fail(WM_EINVAL, "negative batch");
-    if (prec != WM_F32 && prec != WM_BF16 && prec != WM_FP8_E4M3) return fail(WM_EINVAL, "unknown precision");
     if (B == 0) return WM_OK;
-    if (!q || !k || !v || !rpb || !out) return fail(WM_EINVAL, "NULL tensor");
-    const long T = (long)g->Z * g->Y * g->X;
-    const bool fp8 = prec == WM_FP8_E4M3;
-    if (fp8 && B > 64) return fail(WM_EINVAL, "FP8 attention takes at most 64 states per call");
-    const size_t tbl_bytes = (size_t)(fp8 ? B : 1) * g->heads * NAT_TBL_WS_FLOATS * 4;
-    rc = ctx_reserve(ctx, tbl_bytes + (fp8 ? (size_t)AMAX_SHARDS * AMAX_STRIDE * 4 : 0));
+    rc = ctx_reserve(ctx, need);
     if (rc) return rc;
-    NatArgs a{};
-    a.q = q; a.k = k; a.v = v;
-    a.bs = T * g->C; a.ts = g->C; a.hs = 32;
-    a.out = out; a.obs = T * g->C; a.ots = g->C;
-    a.rpb = rpb;
-    a.qscale = LOG2E / std::sqrt(32.0f);
-    a.bscale = LOG2E;
-    a.B = B; a.Z = g->Z; a.Y = g->Y; a.X = g->X; a.H = g->heads;
-    a.Kz = g->Kz; a.Ky = g->Ky; a.Kx = g->Kx; a.periodic = g->periodic_mask;
-    a.tbl_ws = (float *)ctx->ws;
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e;
-    if (fp8) {
-        if (!fp8_attention_applies(g, B, g->C))
-            return fail(WM_EINVAL, "FP8 attention needs lon-periodic only, a 5x7x7, 3x5x5 or 3x3x3 window "
-                                   "and lon >= 8 + Kx - 1");
-        unsigned *amax = (unsigned *)((char *)ctx->ws + tbl_bytes);
-        if ((e = launch_zero_u32(amax, (size_t)AMAX_SHARDS * AMAX_STRIDE, s)) != hipSuccess) return hip_fail(e, "zero");
-        const void *src[3] = {q, k, v};
-        for (int i = 0; i < 3; ++i)
-            if ((e = launch_amax_bf16(src[i], (size_t)T * g->C, B, amax + i, 3, s)) != hipSuccess)
-                return hip_fail(e, "amax");
-        if ((e = launch_amax_fold(amax, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
-        a.amax = (const float *)amax;
-        a.amax_stride = 3;
-    }
-    e = launch_nat(a, prec != WM_F32, s);
-    return e == hipSuccess ? WM_OK : hip_fail(e, "nat launch");
+    return nat_forward_into(g, B, prec, q, k, v, rpb, out, ctx->ws, (hipStream_t)stream);
 }
 
 int wm_layernorm(int M, int C, const float *x, const float *gamma, const float *beta, float eps,

@@ -64,6 +64,12 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int ctx_reserve(wm_ctx *ctx, size_t bytes);
 bool fp8_attention_applies(const wm_grid *g, int B, long ts);
+// wm_nat_forward in two parts: argument checks (and the scratch bytes
+// needed), then the launches with the scratch at a given device address.
+int nat_forward_check(const wm_grid *g, int B, wm_precision prec, const void *q, const void *k, const void *v,
+                      const float *rpb, void *out, size_t *ws_need);
+int nat_forward_into(const wm_grid *g, int B, wm_precision prec, const void *q, const void *k, const void *v,
+                     const float *rpb, void *out, void *ws, hipStream_t s);
 
 
 // Bytes of workspace a block of processor p needs for B states.

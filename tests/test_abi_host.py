@@ -114,6 +114,28 @@ def test_fp8_processor_needs_e4m3_attention_without_gpu(wm):
     assert b"ctx" in L.wm_last_error()
 
 
+def test_nat_forward_noalloc_limits_without_gpu(wm):
+    """The no-allocation attention entry point checks its arguments like
+    wm_nat_forward and refuses work whose scratch exceeds its fixed array,
+    before touching a device."""
+    L = wm.lib()
+    einval = wm_status("WM_EINVAL")
+    assert wm.WM_NAT_NOALLOC_SCRATCH_BYTES == int(eval(re.search(
+        r"#define WM_NAT_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)",
+        open(os.path.join(ROOT, "include", "wm.h")).read()).expand(r"\1 << \2")))
+    g = wm.wm_grid(8, 90, 180, 1024, 32, 5, 7, 7, 4)
+    # FP8: B * heads * 8 KiB + 128 KiB of scratch; 16 states x 32 heads need 4.1 MiB
+    assert L.wm_nat_forward_noalloc(ctypes.byref(g), 16, 2, 1, 1, 1, 1, 1, None) == einval
+    assert b"exceeds" in L.wm_last_error(), L.wm_last_error()
+    # the same checks as wm_nat_forward come first
+    bad = wm.wm_grid(8, 90, 180, 512, 16, 4, 7, 7, 4)
+    assert L.wm_nat_forward_noalloc(ctypes.byref(bad), 1, 1, 1, 1, 1, 1, 1, None) == einval
+    assert L.wm_nat_forward_noalloc(ctypes.byref(g), 1, 1, None, 1, 1, 1, 1, None) == einval
+    assert b"NULL" in L.wm_last_error()
+    # nothing to do: no device needed
+    assert L.wm_nat_forward_noalloc(ctypes.byref(g), 0, 1, None, None, None, None, None, None) == 0
+
+
 def test_serve_validation_without_gpu(wm):
     L = wm.lib()
     einval = wm_status("WM_EINVAL")
