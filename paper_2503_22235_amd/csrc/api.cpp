@@ -68,6 +68,21 @@ bool fp8_attention_applies(const wm_grid *g, int B, long ts) {
     return lds > 0 && lds <= 160 * 1024;
 }
 
+// Whether the bf16 attention on v in the blocked layout (the level-ring
+// kernel) covers grid g at batch B with q/k token stride ts (elements).
+bool ring_attention_applies(const wm_grid *g, int B, long ts) {
+    static float dummy_tbl;
+    NatArgs a{};
+    a.ts = ts;
+    a.B = B; a.Z = g->Z; a.Y = g->Y; a.X = g->X; a.H = g->heads;
+    a.Kz = g->Kz; a.Ky = g->Ky; a.Kx = g->Kx; a.periodic = g->periodic_mask;
+    a.tbl_ws = &dummy_tbl;       // only tested for null
+    a.vt = 1;
+    a.xp = v_blocked_xp(g->X);
+    const size_t lds = nat_tile_lds_bytes(a);
+    return lds > 0 && lds <= 160 * 1024;
+}
+
 int ctx_reserve(wm_ctx *ctx, size_t bytes) {
     if (bytes <= ctx->ws_bytes) return WM_OK;
     hipError_t e;
@@ -91,7 +106,7 @@ int ctx_reserve(wm_ctx *ctx, size_t bytes) {
 // Argument checks of the attention entry points; *ws_need receives the
 // scratch bytes nat_forward_into uses (bias tables, FP8 amax slots).
 int nat_forward_check(const wm_grid *g, int B, wm_precision prec, const void *q, const void *k, const void *v,
-                      const float *rpb, void *out, size_t *ws_need) {
+                      const float *rpb, void *out, bool blocked_v, size_t *ws_need) {
     int rc = validate_grid(g, false);
     if (rc) return rc;
     if (B < 0) return fail(WM_EINVAL, "negative batch");
@@ -100,6 +115,8 @@ int nat_forward_check(const wm_grid *g, int B, wm_precision prec, const void *q,
     if (fp8 && B > 64) return fail(WM_EINVAL, "FP8 attention takes at most 64 states per call");
     *ws_need = (size_t)(fp8 ? B : 1) * g->heads * NAT_TBL_WS_FLOATS * 4 +
                (fp8 ? (size_t)AMAX_SHARDS * AMAX_STRIDE * 4 : 0);
+    if (blocked_v && prec == WM_BF16 && B > 0 && ring_attention_applies(g, B, g->C))
+        *ws_need += (size_t)B * g->Z * g->Y * v_blocked_xp(g->X) * g->C * 2;
     if (B == 0) return WM_OK;
     if (!q || !k || !v || !rpb || !out) return fail(WM_EINVAL, "NULL tensor");
     if (fp8 && !fp8_attention_applies(g, B, g->C))
@@ -111,7 +128,7 @@ int nat_forward_check(const wm_grid *g, int B, wm_precision prec, const void *q,
 // Enqueue the attention of wm_nat_forward (arguments already checked by
 // nat_forward_check, B > 0) with its scratch at device address ws.
 int nat_forward_into(const wm_grid *g, int B, wm_precision prec, const void *q, const void *k, const void *v,
-                     const float *rpb, void *out, void *ws, hipStream_t s) {
+                     const float *rpb, void *out, bool blocked_v, void *ws, hipStream_t s) {
     const long T = (long)g->Z * g->Y * g->X;
     const bool fp8 = prec == WM_FP8_E4M3;
     const size_t tbl_bytes = (size_t)(fp8 ? B : 1) * g->heads * NAT_TBL_WS_FLOATS * 4;
@@ -136,6 +153,14 @@ int nat_forward_into(const wm_grid *g, int B, wm_precision prec, const void *q, 
         if ((e = launch_amax_fold(amax, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
         a.amax = (const float *)amax;
         a.amax_stride = 3;
+    }
+    if (blocked_v && prec == WM_BF16 && ring_attention_applies(g, B, g->C)) {
+        // v copied to the blocked layout (after the tables), read by the level-ring kernel
+        void *vb = (char *)ws + tbl_bytes;
+        a.xp = v_blocked_xp(g->X);
+        if ((e = launch_v_blocked(a, vb, s)) != hipSuccess) return hip_fail(e, "v to blocked layout");
+        a.v = vb;
+        a.vt = 1;
     }
     e = launch_nat(a, prec != WM_F32, s);
     return e == hipSuccess ? WM_OK : hip_fail(e, "nat launch");
@@ -236,13 +261,13 @@ int wm_nat_indices(const wm_grid *g, int *dev_out, void *stream) {
 int wm_nat_forward(wm_ctx *ctx, const wm_grid *g, int B, wm_precision prec, const void *q, const void *k,
                    const void *v, const float *rpb, void *out, void *stream) {
     size_t need = 0;
-    int rc = nat_forward_check(g, B, prec, q, k, v, rpb, out, &need);
+    int rc = nat_forward_check(g, B, prec, q, k, v, rpb, out, true, &need);
     if (rc) return rc;
     if (!ctx) return fail(WM_EINVAL, "ctx is NULL");
     if (B == 0) return WM_OK;
     rc = ctx_reserve(ctx, need);
     if (rc) return rc;
-    return nat_forward_into(g, B, prec, q, k, v, rpb, out, ctx->ws, (hipStream_t)stream);
+    return nat_forward_into(g, B, prec, q, k, v, rpb, out, true, ctx->ws, (hipStream_t)stream);
 }
 
 int wm_layernorm(int M, int C, const float *x, const float *gamma, const float *beta, float eps,
@@ -366,8 +391,9 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
         // source [in][out] -> device [out][in] (bf16 and e4m3 with pr: rows
         // permuted within groups of 32 by perm_row); returns the fp8 dequant
         // scale
-        auto put_wt = [&](const float *s, int in, int outn, const void **dst, bool q8, bool pr) -> float {
-            auto src_col = [&](int o) { return pr ? perm_row(o) : o; };
+        // pr_rows: rows below it are permuted (perm_row), the rest keep their order
+        auto put_wt = [&](const float *s, int in, int outn, const void **dst, bool q8, int pr_rows) -> float {
+            auto src_col = [&](int o) { return o < pr_rows ? perm_row(o) : o; };
             off = align(off);
             if (q8) {
                 float amax = 0.f;
@@ -418,10 +444,12 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
         put_vec(b_2, C, 1.f, &bw.b_2);
         // QKV and MLP1 rows permuted (their epilogues store 8 features per
         // lane); the residual GEMMs keep the natural order
-        bw.dq_qkv = put_wt(w_qkv, C, 3 * C, &bw.w_qkv, fp8, true);
-        put_wt(w_o, C, C, &bw.w_o, false, false);
-        bw.dq_1 = put_wt(w_1, C, F, &bw.w_1, fp8, true);
-        bw.dq_2 = put_wt(w_2, F, C, &bw.w_2, fp8, false);
+        // (bf16: the V rows of W_qkv keep their order; the V tiles of the
+        // projection write the blocked layout with swapped operands)
+        bw.dq_qkv = put_wt(w_qkv, C, 3 * C, &bw.w_qkv, fp8, fp8 ? 3 * C : 2 * C);
+        put_wt(w_o, C, C, &bw.w_o, false, 0);
+        bw.dq_1 = put_wt(w_1, C, F, &bw.w_1, fp8, F);
+        bw.dq_2 = put_wt(w_2, F, C, &bw.w_2, fp8, 0);
         if ((e = hipMemcpy(dev, img.data(), blk_bytes, hipMemcpyHostToDevice)) != hipSuccess) {
             (void)hipFree(p->mem);
             delete p;

@@ -41,8 +41,8 @@ __device__ __forceinline__ void epilogue4(const EpiArgs &ep, int M, int N, int m
     const float4 b = *(const float4 *)(ep.bias + n);
     v[0] += b.x; v[1] += b.y; v[2] += b.z; v[3] += b.w;
     if constexpr (epi_qkv(EPI)) {
-        const int part = n / ep.C;
-        const int hc = n - part * ep.C;
+        const int part = ep.part0 + n / ep.C;
+        const int hc = n - (part - ep.part0) * ep.C;
         const int h = hc >> 5, e = hc & 31;
         if (EPI == EPI_QKV_ROPE && part < 2) {
             float r[4] = {v[0], v[1], v[2], v[3]};
@@ -224,7 +224,8 @@ hipError_t launch_gemm(const void *A, const void *W, int M, int N, int K, bool a
                        const EpiArgs &ep, hipStream_t stream) {
     if (M <= 0) return hipSuccess;
     if (a_bf16 && gemm_lds_applies(M, N, K)) return launch_gemm_lds(A, W, M, N, K, epi, ep, stream);
-    if (ep.perm) return hipErrorInvalidValue;   // permuted W rows are read by the LDS kernels only
+    // permuted W rows and the blocked V layout are the LDS kernels' only
+    if (ep.perm || epi == EPI_VT) return hipErrorInvalidValue;
     if (a_bf16) {
         if (N % 128 == 0) return launch_cfg<bf16, 128, 128>(A, W, M, N, K, epi, ep, stream);
         return launch_cfg<bf16, 128, 64>(A, W, M, N, K, epi, ep, stream);

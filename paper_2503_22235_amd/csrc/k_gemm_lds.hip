@@ -165,7 +165,9 @@ __device__ __forceinline__ void wait_stages(int rem) {
 
 // The MFMAs of one K stage for a wave's TM x TN tiles.  FIRST: the stage is
 // the tile's first, so its first k-step adds to zero instead of acc.
-template <bool FIRST, bool FP8, int TM, int TN, int KSTEPS, int BKB>
+// SWAP (bf16): the activation tile is the MFMA "A" operand, so a lane holds
+// four consecutive tokens of one output feature (the blocked V layout).
+template <bool FIRST, bool FP8, int TM, int TN, int KSTEPS, int BKB, bool SWAP = false>
 __device__ __forceinline__ void mma_stage(const unsigned char *sb, const int *aoff, const int *woff,
                                           f32x4 (&acc)[TN][TM]) {
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
@@ -193,8 +195,69 @@ __device__ __forceinline__ void mma_stage(const unsigned char *sb, const int *ao
             for (int j = 0; j < TN; ++j)
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
-                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af[i], FIRST && ks == 0 ? zero : acc[j][i],
-                                                                        0, 0, 0);
+                    acc[j][i] = SWAP ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], wf[j], FIRST && ks == 0 ? zero : acc[j][i],
+                                                                               0, 0, 0)
+                                     : __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af[i], FIRST && ks == 0 ? zero : acc[j][i],
+                                                                               0, 0, 0);
+        }
+    }
+}
+
+// Epilogue of the V projection (EPI_VT, swapped operands): acc[j][i]
+// holds tokens r0 + 16 i + 4 g + (0..3) (chunk rows) of V feature
+// f0 + 16 j + r16 (head f >> 5, channel f & 31); each lane stores its four tokens' values as 8 bytes of
+// the blocked layout (plus the wrapped copies near lon 0 and X).  Rows whose
+// four tokens leave a lat row (X or the state size not a multiple of 4)
+// are stored one by one.
+template <int TM, int TN>
+__device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, int M, int r0, int f0, const f32x4 (&acc)[TN][TM],
+                                            int g, int r16) {
+    float bv[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) bv[j] = ep.bias[f0 + 16 * j + r16];
+    const int X = ep.vX, xp = ep.vxp, YX = ep.vY * ep.vX;
+    const bool quad = (X & 3) == 0 && (ep.T & 3) == 0;
+    bf16 *vt = (bf16 *)ep.vt;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int m4 = r0 + 16 * i + 4 * g;
+        if (m4 >= M) continue;
+        if (quad) {
+            const unsigned mg = (unsigned)(m4 + ep.row0);
+            const unsigned b = udiv(mg, ep.dT), tt = mg - b * (unsigned)ep.T;
+            const unsigned z = udiv(tt, ep.dYX), rr = tt - z * (unsigned)YX;
+            const unsigned y = udiv(rr, ep.dX), x = rr - y * (unsigned)X;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int f = f0 + 16 * j + r16;
+                uint2 u;
+                u.x = pack_bf16x2(fmaf(acc[j][i][0], 1.0f, bv[j]), fmaf(acc[j][i][1], 1.0f, bv[j]));
+                u.y = pack_bf16x2(fmaf(acc[j][i][2], 1.0f, bv[j]), fmaf(acc[j][i][3], 1.0f, bv[j]));
+                bf16 *row = vt + v_blocked_offset(ep.vB, ep.vZ, ep.vY, xp, f >> 5, (int)b, (int)z, (int)y, 0, f & 31);
+                const int i0 = (int)x + 4;
+                *(uint2 *)(row + (size_t)(i0 >> 2) * 128) = u;
+                if (i0 - X >= 0) *(uint2 *)(row + (size_t)((i0 - X) >> 2) * 128) = u;
+                if (i0 + X < xp) *(uint2 *)(row + (size_t)((i0 + X) >> 2) * 128) = u;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (m4 + e >= M) break;
+                const unsigned mg = (unsigned)(m4 + e + ep.row0);
+                const unsigned b = udiv(mg, ep.dT), tt = mg - b * (unsigned)ep.T;
+                const unsigned z = udiv(tt, ep.dYX), rr = tt - z * (unsigned)YX;
+                const unsigned y = udiv(rr, ep.dX), x = rr - y * (unsigned)X;
+                const int i0 = (int)x + 4;
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int f = f0 + 16 * j + r16;
+                    const bf16 v = (bf16)fmaf(acc[j][i][e], 1.0f, bv[j]);
+                    bf16 *row = vt + v_blocked_offset(ep.vB, ep.vZ, ep.vY, xp, f >> 5, (int)b, (int)z, (int)y, 0, f & 31);
+                    row[(size_t)(i0 >> 2) * 128 + (i0 & 3)] = v;
+                    if (i0 - X >= 0) row[(size_t)((i0 - X) >> 2) * 128 + ((i0 - X) & 3)] = v;
+                    if (i0 + X < xp) row[(size_t)((i0 + X) >> 2) * 128 + ((i0 + X) & 3)] = v;
+                }
+            }
         }
     }
 }
@@ -300,6 +363,9 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
 #pragma unroll
     for (int a = 0; a < AHEAD; ++a)
         if (a < S) issue(a, a);
+    // V projection into the blocked layout: swapped operands
+    constexpr bool SWAP = EPI == EPI_VT;
+    static_assert(!(SWAP && FP8), "blocked V comes from bf16 operands");
     for (int t = 0; t < nn; ++t) {
         for (int kt = 0; kt < nk; ++kt) {
             const int st = t * nk + kt;
@@ -317,13 +383,17 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
             // inline zero operand instead of registers cleared in the previous
             // epilogue (not for the FP8 and rotary variants, whose extra
             // registers would spill with a second copy of the stage code)
-            if (ZSTART && kt == 0) mma_stage<ZSTART, FP8, TM, TN, KSTEPS, BKB>(sb, aoff, woff, acc);
-            else mma_stage<false, FP8, TM, TN, KSTEPS, BKB>(sb, aoff, woff, acc);
+            if (ZSTART && kt == 0) mma_stage<ZSTART, FP8, TM, TN, KSTEPS, BKB, SWAP>(sb, aoff, woff, acc);
+            else mma_stage<false, FP8, TM, TN, KSTEPS, BKB, SWAP>(sb, aoff, woff, acc);
         }
         const int n0 = (rw ? tn0 : tn0 + t) * BN;
         const int mt = rw ? m0 + t * BM : m0;    // first row of this tile
+        if constexpr (SWAP) {
+            vt_epilogue<TM, TN>(ep, M, mt + wm * WM, n0 + wn * WN, acc, g, r16);
+            continue;
+        }
         // a feature tile never straddles Q/K/V (C is a multiple of BN)
-        const int part = epi_qkv(EPI) ? n0 / ep.C : 0;
+        const int part = epi_qkv(EPI) ? ep.part0 + n0 / ep.C : 0;
         const size_t qkv_base = (size_t)part * ep.H * ep.Mtot * 32;
         const float qs = part == 0 ? ep.qscale : 1.0f;
         // per-row dequantization (fp8) and per-state amax of the outputs
@@ -403,7 +473,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
                 if (m < M) {
                     if (ep.perm) {
                         const int n = n0 + wn * WN + 16 * j + 8 * g;
-                        a = epilogue8<EPI>(ep, N, mg, n, acc[j][i], acc[j + 1][i], qkv_base, n - part * ep.C, qs,
+                        a = epilogue8<EPI>(ep, N, mg, n, acc[j][i], acc[j + 1][i], qkv_base, n - (part - ep.part0) * ep.C, qs,
                                            dq[i], rc[i], bz[j], bz[j + 1]);
                     } else {
                         const int n = n0 + wn * WN + 16 * j + 4 * g;
@@ -412,9 +482,9 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
                             r0 = rz[i][0];
                             r1 = rz[i][1];
                         }
-                        a = fmaxf(epilogue4<EPI>(ep, N, mg, n, acc[j][i], qkv_base, n - part * ep.C, qs, dq[i],
+                        a = fmaxf(epilogue4<EPI>(ep, N, mg, n, acc[j][i], qkv_base, n - (part - ep.part0) * ep.C, qs, dq[i],
                                                  bz[j], r0),
-                                  epilogue4<EPI>(ep, N, mg, n + 16, acc[j + 1][i], qkv_base, n + 16 - part * ep.C,
+                                  epilogue4<EPI>(ep, N, mg, n + 16, acc[j + 1][i], qkv_base, n + 16 - (part - ep.part0) * ep.C,
                                                  qs, dq[i], bz[j + 1], r1));
                     }
                 }
@@ -459,12 +529,14 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
     // LDS limit of the variants, set once per process (a local static's
     // initialisation is thread-safe; the server thread launches too)
     static const hipError_t attr_err = [] {
-        const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8>,
+        const void *fns[6] = {(const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8>};
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8>,
+                              FP8 ? nullptr : (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_VT, false>};
         for (const void *f : fns) {
+            if (!f) continue;
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
@@ -512,6 +584,10 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
         case EPI_RESID:
             gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
+        case EPI_VT:
+            if constexpr (FP8) return hipErrorInvalidValue;
+            else gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_VT, false><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            break;
         default:
             gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
@@ -544,7 +620,8 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
         const char *v = getenv("WM_GEMM_CFG");
         return v ? atoi(v) : -1;
     }();
-    const bool n256 = N % 256 == 0;
+    // (a QKV feature tile must not straddle two of Q, K and V: BN divides C)
+    const bool n256 = N % 256 == 0 && (!epi_qkv(epi) || ep.C % 256 == 0);
     switch (cfg) {
     case 0: return launch_cfg<128, 128, 128, 2, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
     case 3: return launch_cfg<256, 128, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
@@ -570,7 +647,7 @@ hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, Ep
         const char *v = getenv("WM_GEMM_CFG");
         return v ? atoi(v) : -1;
     }();
-    if (N % 256 == 0 && cfg != 0) {
+    if (N % 256 == 0 && (!epi_qkv(epi) || ep.C % 256 == 0) && cfg != 0) {
         // N = 512 (MLP2 at C = 512): row walk, as in launch_gemm_lds
         if (N == 512) return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, 2, 1);
         return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, wide_tpw(N), 0);

@@ -110,19 +110,41 @@ __global__ void nat_bias_prep(NatArgs p) {
     p.tbl_ws[e] = v;
 }
 
+// Sum over the 4 lanes l, l^16, l^32, l^48 (the lanes that share a query);
+// every one of them gets the same bits (same operand order).
+__device__ __forceinline__ float xsum16_32(float v) {
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// bf16 tile kernel for token-major v.  The V halo sits in LDS as slabs of
+// 1 KB, one per (level, lat) halo row: 4 blocks of 4 lon columns x 32
+// channels x 4 lon (block q holds halo columns 4q .. 4q+3; halo column c is
+// lon 8 tx - 4 + c), transposed through registers while it is staged.
+//
+// Softmax reference: every query's weights are exp2(s - m) with m its own
+// score (the query's key is always in its window), so the chunk walk needs
+// no running maximum; its own weight is 1, so the sum is >= 1.  A score far
+// above m would overflow: the wave then finds the exact maxima in a second
+// pass and runs the walk again from them (the result check is on the sum
+// and the accumulators).
 template <int KZ, int KY, int KX, bool QSCALED>
 __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, int YR, TileDiv dm) {
     constexpr int RX = (KX - 1) / 2;
     constexpr int BY = 2 * KY - 1;
     constexpr int TBL = (2 * KZ - 1) * BY * XT;    // bias table entries
+    constexpr int SX = 4 - RX;                      // query tile tx starts at lon 8 tx - SX
     static_assert(2 + KX - 1 <= 8 && 2 + KY - 1 <= 8, "window too large for the 8-wide group halo");
+    static_assert(TX == 8 && XW == 16, "halo slab layout");
 
     constexpr int TBLP = tbl_padded<KZ, KY, KX>();
     extern __shared__ __align__(16) unsigned char smem[];
     float *tbl = (float *)smem;                                  // [BZ][BY][XT] + a run of -inf
-    const int nslot_max = ZWmax * YR * XW;
-    const int VS = nslot_max + 4;                                // Vt row stride (elements)
-    unsigned char *Vtb = smem + TBLP * 4;                        // [32][VS] bf16
+    unsigned char *Vh = smem + TBLP * 4;                         // [ZWmax * YR] slabs of 1 KB
 
     // ---- tile of this workgroup (XCD-aware order over (b, h, tile)) ----
     const int ntz = (p.Z + TZ - 1) / TZ, nty = (p.Y + TY - 1) / TY, ntx = (p.X + TX - 1) / TX;
@@ -132,101 +154,65 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
     const int L = blockIdx.x;
     const int id = (L & 7) * per + (L >> 3);
     if (id >= total) return;
-    // (tile x, y, z, head, state) from id by multiply-high divisions on
-    // scalar registers (magic numbers from the launcher)
     unsigned t = (unsigned)id, q;
     q = mdiv(t, dm.mx); const int tx = (int)(t - q * (unsigned)ntx); t = q;
     q = mdiv(t, dm.my); const int ty = (int)(t - q * (unsigned)nty); t = q;
     q = mdiv(t, dm.mz); const int tz = (int)(t - q * (unsigned)ntz); t = q;
     q = mdiv(t, dm.mh); const int h = (int)(t - q * (unsigned)p.H);
     const int b = (int)q;
-    const int z0 = tz * TZ, y0 = ty * TY, x0 = tx * TX;
+    const int z0 = tz * TZ, y0 = ty * TY;
+    const int x0 = tx * TX - SX;                   // lon of the tile's first query (may wrap)
+    const int hx0 = tx * TX - 4;                   // lon of halo column 0 (may wrap)
 
     int zlo, zn, ylo, yn;
     clamp_range(z0, TZ, p.Z, KZ, zlo, zn);
     clamp_range(y0, TY, p.Y, KY, ylo, yn);
-    const int xlo = x0 - RX;                       // periodic lon
 
     const bf16 *kb = (const bf16 *)p.k + (size_t)b * p.bs + (size_t)h * p.hs;
-    const bf16 *vb = (const bf16 *)p.v + (size_t)b * p.bs + (size_t)h * p.hs;
     const bf16 *qb = (const bf16 *)p.q + (size_t)b * p.bs + (size_t)h * p.hs;
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
+    // ---- V halo slabs: (hz, hy) for hz < zn, hy < YR; rows past the halo
+    // repeat its last lat row (finite values: their keys are masked, and
+    // 0 x V must stay 0) ----
+    {
+        // item = (slab, lon block qb4, channel chunk c): 4 tokens x 8 channels,
+        // written as 8 runs of (channel, 4 lon)
+        const bf16 *vb = (const bf16 *)p.v + (size_t)b * p.bs + (size_t)h * p.hs;
+        const int nitem = zn * YR * 16;
+        for (int it = tid; it < nitem; it += 256) {
+            const int sl = it >> 4, qb4 = (it >> 2) & 3, c = it & 3;
+            const int hz = sl / YR, hy = sl - hz * YR;
+            const int yy = min(ylo + hy, ylo + yn - 1);
+            const long rowt = ((long)(zlo + hz) * p.Y + yy) * p.X;
+            uint4 u[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int xc = hx0 + 4 * qb4 + e;
+                xc = xc < 0 ? xc + p.X : (xc >= p.X ? xc - p.X : xc);
+                u[e] = *(const uint4 *)(vb + (rowt + xc) * p.ts + 8 * c);
+            }
+            const unsigned w0[4] = {u[0].x, u[0].y, u[0].z, u[0].w}, w1[4] = {u[1].x, u[1].y, u[1].z, u[1].w};
+            const unsigned w2[4] = {u[2].x, u[2].y, u[2].z, u[2].w}, w3[4] = {u[3].x, u[3].y, u[3].z, u[3].w};
+            uint2 *dst = (uint2 *)(Vh + sl * 1024 + qb4 * 256 + (8 * c) * 8);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                dst[2 * k] = make_uint2(__builtin_amdgcn_perm(w1[k], w0[k], 0x05040100u),
+                                        __builtin_amdgcn_perm(w3[k], w2[k], 0x05040100u));
+                dst[2 * k + 1] = make_uint2(__builtin_amdgcn_perm(w1[k], w0[k], 0x07060302u),
+                                            __builtin_amdgcn_perm(w3[k], w2[k], 0x07060302u));
+            }
+        }
+    }
     // ---- bias table of this head (prepared by nat_bias_prep) ----
     {
         const uint4 *src = (const uint4 *)(p.tbl_ws + (size_t)h * TBLP);
         for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
     }
-    // 32-bit byte offsets within a head's K or V plane: the launcher keeps
-    // the plane below 2 GiB and a lat row of it below 2^24 bytes, so the row
-    // and column products are 24-bit multiplies.
-    const unsigned utsb = (unsigned)p.ts * 2u;                   // token
-    const unsigned usrow = (unsigned)p.X * utsb;                 // lat row
-    const unsigned uslab = (unsigned)p.Y * usrow;                // level
-    const unsigned urow0 = (unsigned)zlo * uslab + (unsigned)ylo * usrow;   // halo origin (lon 0)
 
-    // ---- V halo, transposed: slot (hz, hy, hx) at (hz YR + hy) XW + hx.
-    // Item = (slot pair, 16-byte chunk c) of one halo row (level, lat): the
-    // 32 items of a row go to 32 consecutive threads (4 lanes read the 2 x 64
-    // contiguous bytes of two neighbouring tokens), so a thread keeps its lon
-    // pair and chunk and walks rows 8 apart.  Loads of a batch are issued
-    // before any store.  Rows yn .. YR-1 of each level are zeroed: the chunk
-    // walk reads them for keys outside every window (weight 0), and 0 x V
-    // must stay 0.
-    {
-        const int nrows = zn * yn;
-        const unsigned ym = (65536u + yn - 1) / yn;          // row / yn == (row * ym) >> 16 (row * yn < 2^16)
-        const int c = tid & 3, pr = (tid >> 2) & 7, rb0 = tid >> 5;
-        int xa = xlo + (2 * pr < TX + KX - 1 ? 2 * pr : 0);
-        int xb = xlo + (2 * pr + 1 < TX + KX - 1 ? 2 * pr + 1 : 0);
-        xa = xa < 0 ? xa + p.X : (xa >= p.X ? xa - p.X : xa);
-        xb = xb < 0 ? xb + p.X : (xb >= p.X ? xb - p.X : xb);
-        const unsigned oa = mul24((unsigned)xa, utsb) + 16u * c, ob = mul24((unsigned)xb, utsb) + 16u * c;
-        const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(vb), 0, 0x7ffffffe, 0x00020000);
-        unsigned *Vt32 = (unsigned *)Vtb + (8 * c) * (VS >> 1) + pr;
-        for (int rb = rb0; rb < nrows; rb += 8 * LD_BATCH) {
-            uint4 v0[LD_BATCH], v1[LD_BATCH];
-#pragma unroll
-            for (int u = 0; u < LD_BATCH; ++u) {
-                const unsigned row = (unsigned)min(rb + 8 * u, nrows - 1);
-                const unsigned hz = mul24(row, ym) >> 16, hy = row - mul24(hz, (unsigned)yn);
-                const unsigned ro = urow0 + hz * uslab + mul24(hy, usrow);
-                v0[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(vrs, ro + oa, 0, 0));
-                v1[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(vrs, ro + ob, 0, 0));
-            }
-#pragma unroll
-            for (int u = 0; u < LD_BATCH; ++u) {
-                const int row = rb + 8 * u;
-                if (row < nrows) {
-                    const unsigned hz = mul24((unsigned)row, ym) >> 16, hy = (unsigned)row - mul24(hz, (unsigned)yn);
-                    unsigned *vrow = Vt32 + mul24(mul24(hz, (unsigned)YR) + hy, (unsigned)(XW / 2));
-                    vrow[0 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].x, v0[u].x, 0x05040100u);
-                    vrow[1 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].x, v0[u].x, 0x07060302u);
-                    vrow[2 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].y, v0[u].y, 0x05040100u);
-                    vrow[3 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].y, v0[u].y, 0x07060302u);
-                    vrow[4 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].z, v0[u].z, 0x05040100u);
-                    vrow[5 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].z, v0[u].z, 0x07060302u);
-                    vrow[6 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].w, v0[u].w, 0x05040100u);
-                    vrow[7 * (VS >> 1)] = __builtin_amdgcn_perm(v1[u].w, v0[u].w, 0x07060302u);
-                }
-            }
-        }
-        if (yn < YR) {
-            unsigned *V0 = (unsigned *)Vtb;
-            const int gap = (YR - yn) * (XW / 2);              // dword columns per level
-            const unsigned gm = 0xffffffffu / (unsigned)gap + 1u;   // col / gap == mulhi(col, gm) (col * gap < 2^32)
-            const int nz = zn * gap * 32;
-            for (int e = tid; e < nz; e += 256) {
-                const int d = e & 31, col = e >> 5;
-                const int hz = (int)__umulhi((unsigned)col, gm), cg = col - hz * gap;
-                V0[d * (VS >> 1) + (hz * YR + yn) * (XW / 2) + cg] = 0u;
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- per wave: lat group (wave & 1), lon groups 2*(wave>>1) + {0,1} ----
-    const int lane = tid & 63, wave = tid >> 6;
+    // ---- per wave: lat group pair (wave & 1), lon groups 2*(wave>>1) + {0,1} ----
     const int g = lane >> 4, r16 = lane & 15;
     const int y0g = y0 + 2 * (wave & 1);
     const int gxa = 2 * (wave >> 1);
@@ -242,173 +228,483 @@ __global__ __launch_bounds__(256, 2) void nat_tile_kernel(NatArgs p, int ZWmax, 
     const int zb = zlo - zc + KZ - 1;
     const int yb = ylg - yc + KY - 1;
 
-    // Validity of this lane's key rows for its query: lat row part (chunk
-    // half hf, MFMA block j) is loop-invariant; the level part is tested
-    // per level.  Both are lane masks, so combining them is scalar work.
+    // Key (block j, lane slot 4g + i) of a chunk (hz, hf) is lat row
+    // 4hf + j + 2(g >> 1) of the group halo and lon column 4(g & 1) + i.
     bool oky[2][2];
 #pragma unroll
     for (int hf = 0; hf < 2; ++hf)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-            oky[hf][j] = (unsigned)(4 * hf + 2 * j + (g >> 1) - wy) < (unsigned)KY;
-    // bias table index of this lane's first key at level 0 of the halo
-    const int tb_lane = (zb * BY + yb + (g >> 1)) * XT + 4 * (g & 1) - xrel + 1;
+            oky[hf][j] = (unsigned)(4 * hf + j + 2 * (g >> 1) - wy) < (unsigned)KY;
+    const int tb_lane = (zb * BY + yb + 2 * (g >> 1)) * XT + 4 * (g & 1) - xrel + 1;
 
-    // K operand: key 16j + r16 of a chunk = lat row 4hf + 2j + (r16 >> 3),
-    // lon column r16 & 7 of the group halo, read from global memory (byte
-    // offsets within level zlo; the level advances through the scalar offset).
-    const __amdgpu_buffer_rsrc_t krs = __builtin_amdgcn_make_buffer_rsrc(
-        uniform_ptr(kb), 0, 0x7ffffffe, 0x00020000);
-    const int tsb = (int)p.ts * 2;                          // token stride, bytes
+    // K operand: key 16j + r16 = lat row 4hf + j + 2 (r16 >> 3), lon column
+    // r16 & 7 of the group halo, from global memory (byte offsets within level
+    // zlo; the level advances through the scalar offset).
+    const unsigned utsb = (unsigned)p.ts * 2u;
+    const unsigned usrow = (unsigned)p.X * utsb;
+    const unsigned urow0 = (unsigned)zlo * ((unsigned)p.Y * usrow) + (unsigned)ylo * usrow;
+    const __amdgpu_buffer_rsrc_t krs = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(kb), 0, 0x7ffffffe, 0x00020000);
+    const int tsb = (int)p.ts * 2;
     int kofs[4][2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int hyk = min(4 * (q >> 1) + 2 * (q & 1) + (r16 >> 3) + dy, yn - 1);
+    for (int qq = 0; qq < 4; ++qq) {
+        const int hyk = min(4 * (qq >> 1) + (qq & 1) + 2 * (r16 >> 3) + dy, yn - 1);
 #pragma unroll
         for (int G = 0; G < 2; ++G) {
-            int xk = xlo + (r16 & 7) + GX * (gxa + G);
+            int xk = hx0 + (r16 & 7) + GX * (gxa + G);
             xk = xk < 0 ? xk + p.X : (xk >= p.X ? xk - p.X : xk);
-            kofs[q][G] = (int)(urow0 + mul24((unsigned)hyk, usrow) + mul24((unsigned)xk, utsb)) + 16 * g;
+            kofs[qq][G] = (int)(urow0 + mul24((unsigned)hyk, usrow) + mul24((unsigned)xk, utsb)) + 16 * g;
         }
     }
     const int kslab = p.Y * p.X * tsb;
-    // V^T operand (keys 16j + 4g + i): lane base at level 0 for the two
-    // 16-channel halves tt; lat row, group and key offsets are immediates.
-    const int vbase0 = (r16 * VS + ((g >> 1) + dy) * XW + 4 * (g & 1) + GX * gxa) * 2;
-    const int vbase1 = vbase0 + 16 * VS * 2;
-    const int vslab = YR * XW * 2;
+    // V^T operand: lane base of slab (hz, dy + 2 (g >> 1)), lon block
+    // (wave >> 1) + (g & 1), channel r16; group 0 reads lon columns 0..3 of
+    // that block, group 1 columns 2, 3 of it and 0, 1 of the next.
+    const int vbase = ((dy + 2 * (g >> 1)) * 1024) + ((wave >> 1) + (g & 1)) * 256 + r16 * 8;
+    const int vslab = YR * 1024;
 
-    // Q fragments of the two groups
+    // Q fragments and the queries' own scores
     bf16x8 qf[2];
     long qtok[2];
     bool act[2];
+    float mref[2];
 #pragma unroll
     for (int G = 0; G < 2; ++G) {
-        const int xq = x0 + GX * (gxa + G) + xrel;
-        act[G] = zq < p.Z && yq < p.Y && xq < p.X;
-        const int xc = min(xq, p.X - 1);
+        const int xp_ = x0 + GX * (gxa + G) + xrel;               // query lon before wrapping
+        act[G] = zq < p.Z && yq < p.Y && xp_ < p.X - SX;
+        const int xc = xp_ < 0 ? xp_ + p.X : (xp_ >= p.X ? xp_ - p.X : xp_);
         qtok[G] = (long)mul24(mul24((unsigned)zc, (unsigned)p.Y) + (unsigned)yc, (unsigned)p.X) + xc;
         qf[G] = *(const bf16x8 *)(qb + qtok[G] * p.ts + 8 * g);
+        const bf16x8 ks = *(const bf16x8 *)(kb + qtok[G] * p.ts + 8 * g);
+        float sd = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sd = fmaf(bf2f(qf[G][e]), bf2f(ks[e]), sd);
+        mref[G] = xsum16_32(sd);
+    }
+    __syncthreads();     // V halo (and table) in LDS
+    {
+        const float tcenter = tbl[((KZ - 1) * BY + KY - 1) * XT + 1 + RX];   // bias at offset (0, 0, 0)
+#pragma unroll
+        for (int G = 0; G < 2; ++G) mref[G] = QSCALED ? mref[G] + tcenter : (mref[G] + tcenter) * p.qscale;
     }
 
-    f32x4 oacc[2][2], lacc[2];
-    float mref[2], thr[2];          // reference maxima and the level that moves them
-#pragma unroll
-    for (int G = 0; G < 2; ++G) {
-        oacc[G][0] = oacc[G][1] = lacc[G] = f32x4{0.f, 0.f, 0.f, 0.f};
-        mref[G] = -1e30f;
-        thr[G] = -1e30f;
-    }
     // all-ones operand of the row-sum MFMA, kept in vector registers (the
     // empty asm hides the constant, so it is not rematerialized per chunk)
     uint4 ones_u = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);
     asm volatile("" : "+v"(ones_u.x), "+v"(ones_u.y), "+v"(ones_u.z), "+v"(ones_u.w));
     const bf16x8 ones = __builtin_bit_cast(bf16x8, ones_u);
 
-    // K fragments rotate through four register sets, two chunks ahead:
-    // chunk (hz, hf) uses kreg[2 (hz & 1) + hf] while chunk (hz + 1, hf) is
-    // in flight into kreg[2 (~hz & 1) + hf] (the last level reloads itself).
-    // Levels go two per loop iteration so that the set indices are constants.
-    bf16x8 kreg[4][2][2];
+    f32x4 oacc[2][2], lacc[2];
+    for (int pass = 0;; ++pass) {
 #pragma unroll
-    for (int G = 0; G < 2; ++G)
+        for (int G = 0; G < 2; ++G) oacc[G][0] = oacc[G][1] = lacc[G] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // K fragments rotate through four register sets, two chunks ahead:
+        // chunk (hz, hf) uses kreg[2 (hz & 1) + hf] while chunk (hz + 1, hf)
+        // is in flight into kreg[2 (~hz & 1) + hf] (the last level reloads
+        // itself).  Levels go two per iteration so the set indices are constants.
+        bf16x8 kreg[4][2][2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            kreg[0][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(krs, kofs[j][G], 0, 0));
-            kreg[1][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(krs, kofs[2 + j][G], 0, 0));
-        }
-
-    for (int hz0 = 0; hz0 < zn; hz0 += 2)
+        for (int G = 0; G < 2; ++G)
 #pragma unroll
-    for (int lv = 0; lv < 2; ++lv) {
-        const int hz = hz0 + lv;
-        if (hz >= zn) break;                 // uniform
-        const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
-        const unsigned char *vz0 = Vtb + vbase0 + hz * vslab;
-        const unsigned char *vz1 = Vtb + vbase1 + hz * vslab;
-        const int tbh = tb_lane + hz * BY * XT;
+            for (int j = 0; j < 2; ++j) {
+                kreg[0][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(krs, kofs[j][G], 0, 0));
+                kreg[1][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(krs, kofs[2 + j][G], 0, 0));
+            }
+        for (int hz0 = 0; hz0 < zn; hz0 += 2)
 #pragma unroll
-        for (int hf = 0; hf < 2; ++hf) {
-            const int ks = 2 * lv + hf;          // this chunk's K set
-            {   // chunk (hz + 1, hf) into the set of (hz - 1, hf)
-                // uniform; readfirstlane lets the scalar offset take it directly
-                const int soff = __builtin_amdgcn_readfirstlane(min(hz + 1, zn - 1) * kslab);
+        for (int lv = 0; lv < 2; ++lv) {
+            const int hz = hz0 + lv;
+            if (hz >= zn) break;                 // uniform
+            const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
+            const unsigned char *vz = Vh + vbase + hz * vslab;
+            const int tbh = tb_lane + hz * BY * XT;
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                const int ks = 2 * lv + hf;
+                {   // chunk (hz + 1, hf) into the set of (hz - 1, hf)
+                    const int soff = __builtin_amdgcn_readfirstlane(min(hz + 1, zn - 1) * kslab);
+#pragma unroll
+                    for (int G = 0; G < 2; ++G)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            kreg[ks ^ 2][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
+                                krs, kofs[2 * hf + j][G], soff, 0));
+                }
+                // bias + mask tile (shared by both groups)
+                f32x4 binit[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int a = (okz && oky[hf][j]) ? tbh : TBL;
+                    const float *tp = tbl + a + (4 * hf + j) * XT;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) binit[j][i] = tp[i];
+                }
+                bf16x8 pb[2];
 #pragma unroll
                 for (int G = 0; G < 2; ++G)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        kreg[ks ^ 2][G][j] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
-                            krs, kofs[2 * hf + j][G], soff, 0));
-            }
-            // bias + mask tile (shared by both groups); masked rows read
-            // the run of -inf past the table
-            f32x4 binit[2];
+                    for (int j = 0; j < 2; ++j) {
+                        f32x4 sc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kreg[ks][G][j], qf[G], binit[j], 0, 0, 0);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int a = (okz && oky[hf][j]) ? tbh : TBL;
-                const float *tp = tbl + a + (4 * hf + 2 * j) * XT;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) binit[j][i] = tp[i];
-            }
-            // scores of both groups
-            f32x4 s[2][2];
-            float cm[2];
-#pragma unroll
-            for (int G = 0; G < 2; ++G)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    s[G][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kreg[ks][G][j], qf[G], binit[j], 0, 0, 0);
-                    if constexpr (!QSCALED) {
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) s[G][j][i] *= p.qscale;
+                        for (int i = 0; i < 4; ++i) {
+                            const float sv = QSCALED ? sc[i] : sc[i] * p.qscale;
+                            pb[G][4 * j + i] = (bf16)__builtin_amdgcn_exp2f(sv - mref[G]);
+                        }
                     }
-                }
-#pragma unroll
-            for (int G = 0; G < 2; ++G)
-                cm[G] = max3f(max3f(s[G][0][0], s[G][0][1], s[G][0][2]), max3f(s[G][0][3], s[G][1][0], s[G][1][1]),
-                              max2f(s[G][1][2], s[G][1][3]));
-            // Move the reference maxima only when some lane's scores exceed
-            // them by TAU; the new maximum is taken over the 4 lanes that
-            // share each query, so all of them keep the same reference.
-            if (__builtin_amdgcn_ballot_w64(cm[0] > thr[0] || cm[1] > thr[1])) {
-#pragma unroll
-                for (int G = 0; G < 2; ++G) {
-                    const float mn = max2f(mref[G], xmax16_32(cm[G]));
-                    const float al = __builtin_amdgcn_exp2f(mref[G] - mn);
-                    mref[G] = mn;
-                    thr[G] = mn + TAU;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        oacc[G][0][i] *= al;
-                        oacc[G][1][i] *= al;
-                        lacc[G][i] *= al;
-                    }
-                }
-            }
-            bf16x8 pb[2];
-#pragma unroll
-            for (int G = 0; G < 2; ++G)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        pb[G][4 * j + i] = (bf16)__builtin_amdgcn_exp2f(s[G][j][i] - mref[G]);
-#pragma unroll
-            for (int G = 0; G < 2; ++G) {
+                const unsigned char *vr = vz + 4 * hf * 1024;
 #pragma unroll
                 for (int tt = 0; tt < 2; ++tt) {
-                    const unsigned char *vz = tt ? vz1 : vz0;
-                    uint4 w;
-                    w.x = *(const unsigned *)(vz + (4 * hf) * XW * 2 + 4 * G);
-                    w.y = *(const unsigned *)(vz + (4 * hf) * XW * 2 + 4 * G + 4);
-                    w.z = *(const unsigned *)(vz + (4 * hf + 2) * XW * 2 + 4 * G);
-                    w.w = *(const unsigned *)(vz + (4 * hf + 2) * XW * 2 + 4 * G + 4);
-                    oacc[G][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w), pb[G],
-                                                                          oacc[G][tt], 0, 0, 0);
+                    uint4 w0, w1;
+                    {   // group 0: lon columns 0..3 of the lane's block, rows j = 0, 1
+                        const uint2 a0 = *(const uint2 *)(vr + 128 * tt);
+                        const uint2 a1 = *(const uint2 *)(vr + 128 * tt + 1024);
+                        w0 = make_uint4(a0.x, a0.y, a1.x, a1.y);
+                    }
+                    {   // group 1: columns 2, 3 of the block and 0, 1 of the next
+                        const unsigned char *v1 = vr + 128 * tt + 4;
+                        w1 = make_uint4(*(const unsigned *)v1, *(const unsigned *)(v1 + 252),
+                                        *(const unsigned *)(v1 + 1024), *(const unsigned *)(v1 + 1276));
+                    }
+                    oacc[0][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w0), pb[0],
+                                                                          oacc[0][tt], 0, 0, 0);
+                    oacc[1][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w1), pb[1],
+                                                                          oacc[1][tt], 0, 0, 0);
                 }
-                lacc[G] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, pb[G], lacc[G], 0, 0, 0);
+#pragma unroll
+                for (int G = 0; G < 2; ++G)
+                    lacc[G] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, pb[G], lacc[G], 0, 0, 0);
             }
         }
+        // The query's own weight is 1, so the sum is >= 1; a sum above 2^96
+        // or a non-finite accumulator means a score far above the reference.
+        bool bad = false;
+#pragma unroll
+        for (int G = 0; G < 2; ++G) {
+            bad |= !(lacc[G][0] <= 0x1p96f);
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bad |= !__builtin_isfinite(oacc[G][tt][i]);
+        }
+        if (pass == 1 || !__builtin_amdgcn_ballot_w64(bad)) break;
+        // exact maxima of the wave's queries, then the walk again
+        float mx[2] = {-INFINITY, -INFINITY};
+        for (int hz = 0; hz < zn; ++hz) {
+            const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
+            const int tbh = tb_lane + hz * BY * XT;
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int a = (okz && oky[hf][j]) ? tbh : TBL;
+                    const float *tp = tbl + a + (4 * hf + j) * XT;
+                    f32x4 bi;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) bi[i] = tp[i];
+#pragma unroll
+                    for (int G = 0; G < 2; ++G) {
+                        const bf16x8 kf = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
+                            krs, kofs[2 * hf + j][G], hz * kslab, 0));
+                        const f32x4 sc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf[G], bi, 0, 0, 0);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) mx[G] = max2f(mx[G], QSCALED ? sc[i] : sc[i] * p.qscale);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int G = 0; G < 2; ++G) mref[G] = xmax16_32(mx[G]);
+    }
+
+#pragma unroll
+    for (int G = 0; G < 2; ++G) {
+        if (!act[G]) continue;
+        const float inv = 1.0f / lacc[G][0];
+        bf16 *ob = (bf16 *)p.out + (size_t)b * p.obs + (size_t)qtok[G] * p.ots + h * 32;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            f32x4 v = oacc[G][tt];
+            uint2 u;
+            u.x = pack_bf16x2(v[0] * inv, v[1] * inv);
+            u.y = pack_bf16x2(v[2] * inv, v[3] * inv);
+            *(uint2 *)(ob + 16 * tt + 4 * g) = u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// bf16 kernel for v in the blocked layout (the block path): the K and V
+// halos stream through LDS one level at a time.  A level is 10 lat rows of
+// K (16 tokens x 64 bytes per row) and 10 of V (one 1 KB slab per row),
+// written by direct buffer -> LDS loads (5 per wave per level); two level
+// slots alternate, so level hz+1 loads while level hz is computed, and the
+// only vector-memory loads in the walk are those, so a full wait and one
+// barrier per level order them.  45 KB of LDS per workgroup: three
+// workgroups share a CU.  K rows are token-major with the 16-byte channel
+// chunks of token c (halo column) of row R stored at chunk position
+// q ^ kswz(R, c), so the 16 lanes of a fragment read hit distinct banks.
+// Arithmetic, key order and softmax reference are those of nat_tile_kernel.
+constexpr int RING_ROWS = YR_MIN;              // lat rows per level (>= TY + KY - 1)
+constexpr int RING_SLOT = 2 * RING_ROWS * 1024;   // K rows, then V rows
+
+__device__ __forceinline__ int kswz(int R, int c) { return ((c >> 2) & 1) | (((R >> 1) & 1) << 1); }
+
+template <int KZ, int KY, int KX, bool QSCALED>
+__global__ __launch_bounds__(256, 3) void nat_ring_kernel(NatArgs p, TileDiv dm) {
+    constexpr int RX = (KX - 1) / 2;
+    constexpr int BY = 2 * KY - 1;
+    constexpr int TBL = (2 * KZ - 1) * BY * XT;
+    constexpr int SX = 4 - RX;
+    static_assert(2 + KX - 1 <= 8 && 2 + KY - 1 <= 8, "window too large for the 8-wide group halo");
+    static_assert(TY + KY - 1 <= RING_ROWS, "lat halo rows per level");
+    constexpr int TBLP = tbl_padded<KZ, KY, KX>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *tbl = (float *)smem;
+    unsigned char *ring = smem + TBLP * 4;          // [2 slots][K rows | V rows]
+
+    const int ntz = (p.Z + TZ - 1) / TZ, nty = (p.Y + TY - 1) / TY, ntx = (p.X + TX - 1) / TX;
+    const int ntiles = ntz * nty * ntx;
+    const int total = ntiles * p.H * p.B;
+    const int per = (total + 7) >> 3;
+    const int L = blockIdx.x;
+    const int id = (L & 7) * per + (L >> 3);
+    if (id >= total) return;
+    unsigned t = (unsigned)id, q;
+    q = mdiv(t, dm.mx); const int tx = (int)(t - q * (unsigned)ntx); t = q;
+    q = mdiv(t, dm.my); const int ty = (int)(t - q * (unsigned)nty); t = q;
+    q = mdiv(t, dm.mz); const int tz = (int)(t - q * (unsigned)ntz); t = q;
+    q = mdiv(t, dm.mh); const int h = (int)(t - q * (unsigned)p.H);
+    const int b = (int)q;
+    const int z0 = tz * TZ, y0 = ty * TY;
+    const int x0 = tx * TX - SX;
+    const int hx0 = tx * TX - 4;
+
+    int zlo, zn, ylo, yn;
+    clamp_range(z0, TZ, p.Z, KZ, zlo, zn);
+    clamp_range(y0, TY, p.Y, KY, ylo, yn);
+
+    const bf16 *kb = (const bf16 *)p.k + (size_t)b * p.bs + (size_t)h * p.hs;
+    const bf16 *qb = (const bf16 *)p.q + (size_t)b * p.bs + (size_t)h * p.hs;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    // ---- level staging: row r = wave + 4 u (u < 5) of the 20 (K rows 0..9,
+    // V rows 10..19); rows past the halo repeat its last lat row ----
+    const unsigned tsb = (unsigned)p.ts * 2u;       // token stride, bytes
+    const __amdgpu_buffer_rsrc_t krs = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(kb), 0, 0x7ffffffe, 0x00020000);
+    const size_t plane = (size_t)p.Z * p.Y * p.xp * 64;
+    const unsigned char *vp = (const unsigned char *)p.v + ((size_t)h * p.B + b) * plane;
+    const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(vp), 0, (unsigned)plane, 0x00020000);
+    unsigned kcol[3];          // per K row this wave loads: token and chunk byte offset within the row
+    {
+        const int c = lane >> 2, cq = lane & 3;
+        int xk = hx0 + c;
+        xk = xk < 0 ? xk + p.X : (xk >= p.X ? xk - p.X : xk);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int r = wave + 4 * u;    // K row (u < 3 covers rows 0..9 of waves 0, 1 and 0..7 of 2, 3)
+            kcol[u] = (unsigned)xk * tsb + 16u * (unsigned)(cq ^ kswz(r, c));
+        }
+    }
+    const unsigned vcol = 512u * (unsigned)tx + 16u * (unsigned)lane;
+    const unsigned rowb = (unsigned)p.xp * 64u;
+    auto stage = [&](int hz, int slot) {
+        unsigned char *dst = ring + slot * RING_SLOT;
+        const unsigned zr = (unsigned)(zlo + hz) * (unsigned)p.Y;
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+            const int r = wave + 4 * u;
+            if (r < RING_ROWS) {
+                const unsigned yy = (unsigned)min(ylo + r, ylo + yn - 1);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(krs, (lds_void *)(dst + r * 1024), 16,
+                                                         (zr + yy) * (unsigned)p.X * tsb + kcol[u < 3 ? u : 0], 0, 0, 0);
+            } else {
+                const unsigned yy = (unsigned)min(ylo + r - RING_ROWS, ylo + yn - 1);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(vrs, (lds_void *)(dst + r * 1024), 16, (zr + yy) * rowb + vcol, 0, 0, 0);
+            }
+        }
+    };
+    stage(0, 0);
+    {
+        const uint4 *src = (const uint4 *)(p.tbl_ws + (size_t)h * TBLP);
+        for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
+    }
+
+    // ---- per wave: lat group pair (wave & 1), lon groups 2*(wave>>1) + {0,1} ----
+    const int g = lane >> 4, r16 = lane & 15;
+    const int y0g = y0 + 2 * (wave & 1);
+    const int gxa = 2 * (wave >> 1);
+    const int zq = z0 + (r16 >> 2), yq = y0g + ((r16 >> 1) & 1);
+    const int xrel = r16 & 1;
+    const int zc = min(zq, p.Z - 1), yc = min(yq, p.Y - 1);
+    int ylg, yng;
+    clamp_range(min(y0g, p.Y - 1), 2, p.Y, KY, ylg, yng);
+    const int dy = ylg - ylo;
+    const int wz = win_start(zc, p.Z, KZ, false) - zlo;
+    const int wy = win_start(yc, p.Y, KY, false) - ylg;
+    const int zb = zlo - zc + KZ - 1;
+    const int yb = ylg - yc + KY - 1;
+    bool oky[2][2];
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            oky[hf][j] = (unsigned)(4 * hf + j + 2 * (g >> 1) - wy) < (unsigned)KY;
+    const int tb_lane = (zb * BY + yb + 2 * (g >> 1)) * XT + 4 * (g & 1) - xrel + 1;
+    // K operand (key 16 j + r16 = lat row 4hf + j + 2 (r16 >> 3), lon column
+    // r16 & 7 of the group halo): LDS byte offsets within a level slot
+    int kaddr[2][2][2];
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int G = 0; G < 2; ++G) {
+                const int R = dy + 4 * hf + j + 2 * (r16 >> 3), c = GX * (gxa + G) + (r16 & 7);
+                kaddr[hf][j][G] = R * 1024 + c * 64 + 16 * (g ^ kswz(R, c));
+            }
+    // V^T operand (as in nat_tile_kernel), within a level's V rows
+    const int vbase = RING_ROWS * 1024 + (dy + 2 * (g >> 1)) * 1024 + ((wave >> 1) + (g & 1)) * 256 + r16 * 8;
+
+    bf16x8 qf[2];
+    long qtok[2];
+    bool act[2];
+    float mref[2];
+#pragma unroll
+    for (int G = 0; G < 2; ++G) {
+        const int xp_ = x0 + GX * (gxa + G) + xrel;
+        act[G] = zq < p.Z && yq < p.Y && xp_ < p.X - SX;
+        const int xc = xp_ < 0 ? xp_ + p.X : (xp_ >= p.X ? xp_ - p.X : xp_);
+        qtok[G] = (long)mul24(mul24((unsigned)zc, (unsigned)p.Y) + (unsigned)yc, (unsigned)p.X) + xc;
+        qf[G] = *(const bf16x8 *)(qb + qtok[G] * p.ts + 8 * g);
+        const bf16x8 ks = *(const bf16x8 *)(kb + qtok[G] * p.ts + 8 * g);
+        float sd = 0.f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) sd = fmaf(bf2f(qf[G][e]), bf2f(ks[e]), sd);
+        mref[G] = xsum16_32(sd);
+    }
+    __syncthreads();     // bias table and level 0 in LDS
+    {
+        const float tcenter = tbl[((KZ - 1) * BY + KY - 1) * XT + 1 + RX];
+#pragma unroll
+        for (int G = 0; G < 2; ++G) mref[G] = QSCALED ? mref[G] + tcenter : (mref[G] + tcenter) * p.qscale;
+    }
+
+    uint4 ones_u = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);
+    asm volatile("" : "+v"(ones_u.x), "+v"(ones_u.y), "+v"(ones_u.z), "+v"(ones_u.w));
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, ones_u);
+
+    f32x4 oacc[2][2], lacc[2];
+    for (int pass = 0;; ++pass) {
+#pragma unroll
+        for (int G = 0; G < 2; ++G) oacc[G][0] = oacc[G][1] = lacc[G] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int hz0 = 0; hz0 < zn; hz0 += 2)
+#pragma unroll
+        for (int lv = 0; lv < 2; ++lv) {          // level hz0 + lv is in slot lv
+            const int hz = hz0 + lv;
+            if (hz >= zn) break;                  // uniform
+            if (hz > 0) __syncthreads();          // level hz landed; level hz - 1 is done with
+            if (hz + 1 < zn) stage(hz + 1, lv ^ 1);
+            const unsigned char *sl = ring + lv * RING_SLOT;
+            const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
+            const int tbh = tb_lane + hz * BY * XT;
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                f32x4 binit[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int a = (okz && oky[hf][j]) ? tbh : TBL;
+                    const float *tp = tbl + a + (4 * hf + j) * XT;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) binit[j][i] = tp[i];
+                }
+                bf16x8 pb[2];
+#pragma unroll
+                for (int G = 0; G < 2; ++G)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const bf16x8 kf = *(const bf16x8 *)(sl + kaddr[hf][j][G]);
+                        const f32x4 sc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf[G], binit[j], 0, 0, 0);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float sv = QSCALED ? sc[i] : sc[i] * p.qscale;
+                            pb[G][4 * j + i] = (bf16)__builtin_amdgcn_exp2f(sv - mref[G]);
+                        }
+                    }
+                const unsigned char *vr = sl + vbase + 4 * hf * 1024;
+#pragma unroll
+                for (int tt = 0; tt < 2; ++tt) {
+                    uint4 w0, w1;
+                    {
+                        const uint2 a0 = *(const uint2 *)(vr + 128 * tt);
+                        const uint2 a1 = *(const uint2 *)(vr + 128 * tt + 1024);
+                        w0 = make_uint4(a0.x, a0.y, a1.x, a1.y);
+                    }
+                    {
+                        const unsigned char *v1 = vr + 128 * tt + 4;
+                        w1 = make_uint4(*(const unsigned *)v1, *(const unsigned *)(v1 + 252),
+                                        *(const unsigned *)(v1 + 1024), *(const unsigned *)(v1 + 1276));
+                    }
+                    oacc[0][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w0), pb[0],
+                                                                          oacc[0][tt], 0, 0, 0);
+                    oacc[1][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, w1), pb[1],
+                                                                          oacc[1][tt], 0, 0, 0);
+                }
+#pragma unroll
+                for (int G = 0; G < 2; ++G)
+                    lacc[G] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ones, pb[G], lacc[G], 0, 0, 0);
+            }
+        }
+        int bad = 0;
+#pragma unroll
+        for (int G = 0; G < 2; ++G) {
+            bad |= !(lacc[G][0] <= 0x1p96f);
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bad |= !__builtin_isfinite(oacc[G][tt][i]);
+        }
+        // workgroup-uniform decision: the walk has barriers
+        if (!__syncthreads_or(bad) || pass == 1) break;
+        // exact maxima (K from global memory), then the walk again
+        {
+            const unsigned usrow = (unsigned)p.X * tsb;
+            const unsigned urow0 = (unsigned)zlo * ((unsigned)p.Y * usrow) + (unsigned)ylo * usrow;
+            const int kslab = p.Y * p.X * (int)tsb;
+            float mx[2] = {-INFINITY, -INFINITY};
+            for (int hz = 0; hz < zn; ++hz) {
+                const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
+                const int tbh = tb_lane + hz * BY * XT;
+#pragma unroll
+                for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int a = (okz && oky[hf][j]) ? tbh : TBL;
+                        const float *tp = tbl + a + (4 * hf + j) * XT;
+                        f32x4 bi;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) bi[i] = tp[i];
+                        const int hyk = min(4 * hf + j + 2 * (r16 >> 3) + dy, yn - 1);
+#pragma unroll
+                        for (int G = 0; G < 2; ++G) {
+                            int xk = hx0 + (r16 & 7) + GX * (gxa + G);
+                            xk = xk < 0 ? xk + p.X : (xk >= p.X ? xk - p.X : xk);
+                            const unsigned ko = urow0 + (unsigned)hyk * usrow + (unsigned)xk * tsb + 16u * g;
+                            const bf16x8 kf = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(
+                                krs, ko, hz * kslab, 0));
+                            const f32x4 sc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(kf, qf[G], bi, 0, 0, 0);
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) mx[G] = max2f(mx[G], QSCALED ? sc[i] : sc[i] * p.qscale);
+                        }
+                    }
+            }
+#pragma unroll
+            for (int G = 0; G < 2; ++G) mref[G] = xmax16_32(mx[G]);
+        }
+        stage(0, 0);
+        __syncthreads();
     }
 
 #pragma unroll
@@ -809,8 +1105,7 @@ int max_halo(int N, int K, int tsize) {
 
 size_t tile_lds(int Kz, int Ky, int zw, int yr) {
     const int tblp = (((2 * Kz - 1) * (2 * Ky - 1) * XT + NEG_RUN + 3) & ~3);
-    const size_t nslot = (size_t)zw * yr * XW;
-    return (size_t)tblp * 4 + 32 * (nslot + 4) * 2;
+    return (size_t)tblp * 4 + (size_t)zw * yr * 1024;     // table + V halo slabs
 }
 
 template <int KZ, int KY, int KX, bool QSCALED>
@@ -828,6 +1123,60 @@ hipError_t launch_tile_q(const NatArgs &a, hipStream_t stream) {
     const unsigned grid = (unsigned)(((total + 7) >> 3) << 3);
     nat_tile_kernel<KZ, KY, KX, QSCALED><<<grid, 256, lds, stream>>>(a, zw, yr, tile_div(a));
     return hipGetLastError();
+}
+
+size_t ring_lds(int Kz, int Ky) {
+    const int tblp = (((2 * Kz - 1) * (2 * Ky - 1) * XT + NEG_RUN + 3) & ~3);
+    return (size_t)tblp * 4 + 2 * (size_t)RING_SLOT;
+}
+
+template <int KZ, int KY, int KX, bool QSCALED>
+hipError_t launch_ring(const NatArgs &a, hipStream_t stream) {
+    // exactly the dynamic size: the kernel also holds a little static LDS (__syncthreads_or)
+    static const hipError_t attr_err = hipFuncSetAttribute((const void *)nat_ring_kernel<KZ, KY, KX, QSCALED>,
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                           (int)ring_lds(KZ, KY));
+    if (attr_err != hipSuccess) return attr_err;
+    constexpr int TBLP = tbl_padded<KZ, KY, KX>();
+    if (!a.tbl_ready) nat_bias_prep<KZ, KY, KX, QSCALED><<<(a.H * TBLP + 255) / 256, 256, 0, stream>>>(a);
+    const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
+    const long total = (long)ntiles * a.H * a.B;
+    const unsigned grid = (unsigned)(((total + 7) >> 3) << 3);
+    nat_ring_kernel<KZ, KY, KX, QSCALED><<<grid, 256, ring_lds(KZ, KY), stream>>>(a, tile_div(a));
+    return hipGetLastError();
+}
+
+// v [B][T][H][32] (strides bs, ts, hs) -> the blocked layout: one thread per
+// (head, state, level, lat, block of 4 positions, 8 channels).
+__global__ void v_blocked_kernel(const bf16 *__restrict__ v, long bs, long ts, long hs, bf16 *__restrict__ out,
+                                 int B, int Z, int Y, int X, int H, int xp) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nxb = xp >> 2;
+    const long total = (long)H * B * Z * Y * nxb * 4;
+    if (e >= total) return;
+    const int c = (int)(e & 3);
+    long r = e >> 2;
+    const int xb = (int)(r % nxb); r /= nxb;
+    const long zyb = r;                          // ((h B + b) Z + z) Y + y
+    const int y = (int)(r % Y); r /= Y;
+    const int z = (int)(r % Z); r /= Z;
+    const int b = (int)(r % B);
+    const int h = (int)(r / B);
+    uint4 u[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int x = 4 * xb + k - 4;
+        x = ((x % X) + X) % X;
+        u[k] = *(const uint4 *)(v + (size_t)b * bs + (((size_t)z * Y + y) * X + x) * ts + (size_t)h * hs + 8 * c);
+    }
+    const unsigned w0[4] = {u[0].x, u[0].y, u[0].z, u[0].w}, w1[4] = {u[1].x, u[1].y, u[1].z, u[1].w};
+    const unsigned w2[4] = {u[2].x, u[2].y, u[2].z, u[2].w}, w3[4] = {u[3].x, u[3].y, u[3].z, u[3].w};
+    uint2 *dst = (uint2 *)(out + ((size_t)zyb * nxb + xb) * 128 + (8 * c) * 4);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        dst[2 * k] = make_uint2(__builtin_amdgcn_perm(w1[k], w0[k], 0x05040100u), __builtin_amdgcn_perm(w3[k], w2[k], 0x05040100u));
+        dst[2 * k + 1] = make_uint2(__builtin_amdgcn_perm(w1[k], w0[k], 0x07060302u), __builtin_amdgcn_perm(w3[k], w2[k], 0x07060302u));
+    }
 }
 
 size_t tile_lds_fp8(int Kz, int Ky, int zw, int yr) {
@@ -855,6 +1204,10 @@ hipError_t launch_tile_fp8(const NatArgs &a, hipStream_t stream) {
 template <int KZ, int KY, int KX>
 hipError_t launch_tile(const NatArgs &a, hipStream_t stream) {
     if (a.amax) return launch_tile_fp8<KZ, KY, KX>(a, stream);
+    if (a.vt) {
+        if (a.qscale == 1.0f) return launch_ring<KZ, KY, KX, true>(a, stream);
+        return launch_ring<KZ, KY, KX, false>(a, stream);
+    }
     if (a.qscale == 1.0f) return launch_tile_q<KZ, KY, KX, true>(a, stream);
     return launch_tile_q<KZ, KY, KX, false>(a, stream);
 }
@@ -878,6 +1231,13 @@ size_t nat_tile_lds_bytes(const NatArgs &a) {
         for (long d : nt)
             if (total * d >= (1L << 32)) return 0;
     }
+    if (a.vt) {
+        // blocked V: every halo row must be one in-range 1 KB run, and a
+        // (head, state) plane must be addressable with 32-bit offsets
+        if (a.amax || a.xp < v_blocked_xp(a.X)) return 0;
+        if ((long)a.Z * a.Y * a.xp * 64 >= (1L << 31)) return 0;
+    }
+    if (a.vt) return ring_lds(a.Kz, a.Ky);
     const int zw = max_halo(a.Z, a.Kz, TZ), yr = std::max(max_halo(a.Y, a.Ky, TY), YR_MIN);
     return a.amax ? tile_lds_fp8(a.Kz, a.Ky, zw, yr) : tile_lds(a.Kz, a.Ky, zw, yr);
 }
@@ -895,6 +1255,15 @@ hipError_t launch_nat_bias_table(const NatArgs &a, hipStream_t stream) {
     if (a.Kz == 3 && a.Ky == 5 && a.Kx == 5) return bias_table_only<3, 5, 5>(a, stream);
     if (a.Kz == 3 && a.Ky == 3 && a.Kx == 3) return bias_table_only<3, 3, 3>(a, stream);
     return hipErrorNotSupported;
+}
+
+hipError_t launch_v_blocked(const NatArgs &a, void *out, hipStream_t stream) {
+    const long total = (long)a.H * a.B * a.Z * a.Y * (a.xp / 4) * 4;
+    if (total == 0) return hipSuccess;
+    if ((a.xp & 3) || total > 0x7fffffffL) return hipErrorInvalidValue;
+    v_blocked_kernel<<<(unsigned)((total + 255) / 256), 256, 0, stream>>>((const bf16 *)a.v, a.bs, a.ts, a.hs, (bf16 *)out,
+                                                                        a.B, a.Z, a.Y, a.X, a.H, a.xp);
+    return hipGetLastError();
 }
 
 hipError_t launch_nat_tile(const NatArgs &a, hipStream_t stream) {

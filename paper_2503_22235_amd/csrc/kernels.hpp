@@ -21,14 +21,30 @@ enum EpiKind : int {
     EPI_GELU = 1,   // gelu(+bias) -> out [M][N]
     EPI_RESID = 2,  // resid[m][n] += acc + bias (float32 in place)
     EPI_STORE = 3,  // +bias -> out [M][N]
-    EPI_QKV_ROPE = 4  // EPI_QKV with q and k rotated (EpiArgs.rope)
+    EPI_QKV_ROPE = 4, // EPI_QKV with q and k rotated (EpiArgs.rope)
+    EPI_VT = 5        // +bias -> EpiArgs.vt in the blocked V layout (bf16 LDS GEMM only)
 };
 constexpr bool epi_qkv(int e) { return e == EPI_QKV || e == EPI_QKV_ROPE; }
+// Division of n < 2^31 by a fixed d >= 1 as a multiply-high and a shift
+// (Granlund and Montgomery 1994: with l = ceil(log2 d) and
+// m = floor(2^(31+l) / d) + 1, floor(n/d) = floor(n m / 2^(31+l))).
+struct UDiv {
+    unsigned m;
+    int s;          // shift after the multiply-high; -1: d == 1
+};
+inline UDiv udiv_make(unsigned d) {
+    if (d <= 1) return UDiv{0u, -1};
+    int l = 0;
+    while ((1ull << l) < d) ++l;
+    return UDiv{(unsigned)((1ull << (31 + l)) / d + 1), l - 1};
+}
+__device__ __forceinline__ unsigned udiv(unsigned n, UDiv d) { return d.s < 0 ? n : (__umulhi(n, d.m) >> d.s); }
 struct EpiArgs {
     const float *bias;  // [N]
     void *out;          // EPI_QKV / EPI_GELU / EPI_STORE output
     float *resid;       // EPI_RESID target
     int C, H;           // EPI_QKV: model width and heads (d = 32)
+    int part0;          // EPI_QKV: part (0 Q, 1 K, 2 V) of output column 0
     float qscale;       // EPI_QKV: factor on Q columns
     // FP8 operands: acc * (a_amax[state of row] / 448) * w_dequant, or
     // acc * a_dequant * w_dequant when a_amax is null (one scale for all rows)
@@ -53,6 +69,13 @@ struct EpiArgs {
     // Set by the LDS GEMM launchers when they split M into row chunks: the
     // global row of the chunk's row 0 and the total row count.
     int row0, Mtot;
+    // EPI_VT: output feature f (head f >> 5, channel f & 31) goes to `vt`
+    // in the blocked layout of v_blocked_offset (grid vZ x vY x vX, vxp
+    // padded positions, vB states).  Divisors of a row index: tokens per
+    // state (T), per level, per lat row.
+    void *vt;
+    int vB, vZ, vY, vX, vxp;
+    UDiv dT, dYX, dX;
 };
 // Rotary position embedding of cnt consecutive channels e.. (e even) of a
 // q or k head row at global row mg (token mg mod T): channel pair p =
@@ -136,7 +159,24 @@ struct NatArgs {
     // run on e4m3 codes with the scales amax/448.
     const float *amax;
     int amax_stride;
+    // bf16 only: v is in the blocked layout of v_blocked_offset (vt = 1)
+    // with xp padded lon positions per row; q is pre-scaled (qscale = 1)
+    int vt;
+    int xp;
 };
+// Blocked V layout (bf16), written by the QKV projection of bf16
+// processors for the tiled attention kernel: per (head, state, level, lat)
+// a row of xp padded lon positions i, position i holding lon (i - 4) mod X,
+// in blocks of 4 positions x 32 channels x 4 positions (256 bytes), so that
+// the 16 positions 8 tx .. 8 tx + 15 (the halo of query tile tx) are one
+// 1 KB run.  Element offset of (head h, state b, level z, lat y, position
+// i, channel d):
+__host__ __device__ inline size_t v_blocked_offset(int B, int Z, int Y, int xp, int h, int b, int z, int y, int i,
+                                                   int d) {
+    return ((((size_t)h * B + b) * Z + z) * Y + y) * ((size_t)xp * 32) + (size_t)(i >> 2) * 128 + d * 4 + (i & 3);
+}
+// padded positions per row: every tile's 16-position halo run plus the wrap
+inline int v_blocked_xp(int X) { return 8 * ((X + 7) / 8) + 8; }
 constexpr int NAT_TBL_WS_FLOATS = 2048;     // per head, >= padded bias table
 // Picks the LDS-tiled bf16 kernel when it applies, else the generic one.
 hipError_t launch_nat(const NatArgs &a, bool bf16, hipStream_t stream);
@@ -149,6 +189,9 @@ hipError_t launch_nat_generic(const NatArgs &a, bool bf16, hipStream_t stream);
 // LDS bytes of the tiled bf16 kernel for these arguments (0: not applicable).
 size_t nat_tile_lds_bytes(const NatArgs &a);
 hipError_t launch_nat_tile(const NatArgs &a, hipStream_t stream);
+// Copies a.v (bf16, token-major with strides bs, ts, hs) into `out` in the
+// blocked layout of v_blocked_offset with a.xp positions per row.
+hipError_t launch_v_blocked(const NatArgs &a, void *out, hipStream_t stream);
 
 // --- index tables (same window functions as the attention kernels) ------
 hipError_t launch_nat_indices(int Z, int Y, int X, int Kz, int Ky, int Kx,

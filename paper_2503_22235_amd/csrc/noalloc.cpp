@@ -48,7 +48,7 @@ extern "C" int wm_nat_forward_noalloc(const wm_grid *g, int B, wm_precision prec
                                       const void *v, const float *rpb, void *out, void *stream) {
     using namespace wm;
     size_t need = 0;
-    int rc = nat_forward_check(g, B, prec, q, k, v, rpb, out, &need);
+    int rc = nat_forward_check(g, B, prec, q, k, v, rpb, out, false, &need);
     if (rc) return rc;
     if (need > SCRATCH_BYTES)
         return fail(WM_EINVAL, "attention scratch of %zu bytes exceeds the fixed %zu-byte array "
@@ -60,5 +60,5 @@ extern "C" int wm_nat_forward_noalloc(const wm_grid *g, int B, wm_precision prec
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     void *ws = nullptr;
     if ((rc = scratch_address(dev, &ws)) != WM_OK) return rc;
-    return nat_forward_into(g, B, prec, q, k, v, rpb, out, ws, (hipStream_t)stream);
+    return nat_forward_into(g, B, prec, q, k, v, rpb, out, false, ws, (hipStream_t)stream);
 }

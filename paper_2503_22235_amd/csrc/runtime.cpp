@@ -20,8 +20,18 @@ size_t block_workspace_bytes(const wm_processor *p, int B) {
     const size_t esz = p->prec == WM_BF16 ? 2 : 4;
     const size_t big = (3 * C > F ? 3 * C : F);
     const size_t act = (M * C * esz + 255) & ~(size_t)255;
-    const size_t bigb = (M * big * esz + 255) & ~(size_t)255;
+    size_t bigb = (M * big * esz + 255) & ~(size_t)255;
+    if (p->prec == WM_BF16) {
+        // q and k head-major, v in the blocked layout (padded lon)
+        const size_t qkv = 2 * M * C * 2 + (size_t)B * p->g.Z * p->g.Y * v_blocked_xp(p->g.X) * C * 2;
+        bigb = std::max(bigb, al256(qkv));
+    }
     return act + bigb + (size_t)p->g.heads * NAT_TBL_WS_FLOATS * 4;
+}
+
+// Bytes from the start of the block workspace to the bias-table scratch.
+static size_t block_tbl_offset(const wm_processor *p, int B) {
+    return block_workspace_bytes(p, B) - (size_t)p->g.heads * NAT_TBL_WS_FLOATS * 4;
 }
 
 int reserve_block_workspace(wm_ctx *ctx, const wm_processor *p, int B) {
@@ -75,30 +85,11 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     const size_t esz = bf ? 2 : 4;
     char *act = (char *)ctx->ws;
     char *big = act + (((size_t)M * C * esz + 255) & ~(size_t)255);
-    const size_t F3 = (size_t)(3 * C > F ? 3 * C : F);
-    float *tbl_ws = (float *)(big + (((size_t)M * F3 * esz + 255) & ~(size_t)255));
+    float *tbl_ws = (float *)((char *)ctx->ws + block_tbl_offset(p, B));
     hipError_t e;
 
-    int rc;
-#define WM_TIMED(kind, call, what)                                  \
-    if ((rc = prof_begin(ctx, s, kind)) != WM_OK) return rc;        \
-    if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
-    if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
-    WM_TIMED(PK_LN1, launch_layernorm(x, w.ln1_g, w.ln1_b, act, bf, M, C, 1e-5f, s), "LN1")
-    EpiArgs ep{};
-    ep.bias = w.b_qkv;
-    ep.out = big;
-    ep.C = C;
-    ep.H = H;
-    ep.qscale = LOG2E / std::sqrt(32.0f);
-    ep.perm = bf;   // bf16 W_qkv and W_1 are stored with permuted rows (perm_row)
-    if (p->rope_tab) {
-        ep.rope = p->rope_tab;
-        ep.rZ = g.Z; ep.rY = g.Y; ep.rX = g.X;
-        ep.T = T;
-    }
-    WM_TIMED(PK_QKV, launch_gemm(act, w.w_qkv, M, 3 * C, C, bf, p->rope_tab ? EPI_QKV_ROPE : EPI_QKV, ep, s), "QKV")
-
+    // Attention arguments first: bf16 blocks whose grid the tiled kernel
+    // covers take v in the blocked layout, straight from the QKV epilogue.
     NatArgs na{};
     const size_t plane = (size_t)H * M * 32 * esz;
     na.q = big;
@@ -117,6 +108,61 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     na.Kz = g.Kz; na.Ky = g.Ky; na.Kx = g.Kx; na.periodic = g.periodic_mask;
     na.tbl_ws = w.nat_tbl ? w.nat_tbl : tbl_ws;
     na.tbl_ready = w.nat_tbl != nullptr;
+    if (bf) {
+        na.vt = 1;
+        na.xp = v_blocked_xp(g.X);
+        const size_t lds = nat_tile_lds_bytes(na);
+        if (lds == 0 || lds > 160 * 1024) na.vt = 0;
+    }
+
+    int rc;
+#define WM_TIMED(kind, call, what)                                  \
+    if ((rc = prof_begin(ctx, s, kind)) != WM_OK) return rc;        \
+    if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
+    if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
+    WM_TIMED(PK_LN1, launch_layernorm(x, w.ln1_g, w.ln1_b, act, bf, M, C, 1e-5f, s), "LN1")
+    EpiArgs ep{};
+    ep.bias = w.b_qkv;
+    ep.out = big;
+    ep.C = C;
+    ep.H = H;
+    ep.qscale = LOG2E / std::sqrt(32.0f);
+    if (p->rope_tab) {
+        ep.rope = p->rope_tab;
+        ep.rZ = g.Z; ep.rY = g.Y; ep.rX = g.X;
+        ep.T = T;
+    }
+    // bf16: the Q and K columns (W rows permuted by perm_row, head-major
+    // output) and the V columns (W rows in natural order) are two launches;
+    // V goes to the blocked layout when the tiled attention reads it.
+    auto qkv = [&]() -> hipError_t {
+        const EpiKind kqk = p->rope_tab ? EPI_QKV_ROPE : EPI_QKV;
+        if (!bf) return launch_gemm(act, w.w_qkv, M, 3 * C, C, false, kqk, ep, s);
+        EpiArgs eqk = ep;
+        eqk.perm = 1;
+        hipError_t err = launch_gemm(act, w.w_qkv, M, 2 * C, C, true, kqk, eqk, s);
+        if (err != hipSuccess) return err;
+        const void *wv = (const unsigned char *)w.w_qkv + (size_t)2 * C * C * 2;
+        EpiArgs ev{};
+        ev.bias = w.b_qkv + 2 * C;
+        if (na.vt) {
+            ev.vt = (void *)na.v;
+            ev.vB = B; ev.vZ = g.Z; ev.vY = g.Y; ev.vX = g.X; ev.vxp = na.xp;
+            ev.T = T;
+            ev.dT = udiv_make((unsigned)T);
+            ev.dYX = udiv_make((unsigned)(g.Y * g.X));
+            ev.dX = udiv_make((unsigned)g.X);
+            return launch_gemm(act, wv, M, C, C, true, EPI_VT, ev, s);
+        }
+        ev.out = big;
+        ev.C = C;
+        ev.H = H;
+        ev.qscale = 1.0f;
+        ev.part0 = 2;
+        return launch_gemm(act, wv, M, C, C, true, EPI_QKV, ev, s);
+    };
+    WM_TIMED(PK_QKV, qkv(), "QKV")
+
     WM_TIMED(PK_NA, launch_nat(na, bf, s), "NA")
 
     EpiArgs er{};

@@ -66,10 +66,13 @@ int ctx_reserve(wm_ctx *ctx, size_t bytes);
 bool fp8_attention_applies(const wm_grid *g, int B, long ts);
 // wm_nat_forward in two parts: argument checks (and the scratch bytes
 // needed), then the launches with the scratch at a given device address.
+// blocked_v: bf16 attention copies v to the blocked layout in the scratch
+// and runs the level-ring kernel (else the token-major tile kernel).
 int nat_forward_check(const wm_grid *g, int B, wm_precision prec, const void *q, const void *k, const void *v,
-                      const float *rpb, void *out, size_t *ws_need);
+                      const float *rpb, void *out, bool blocked_v, size_t *ws_need);
 int nat_forward_into(const wm_grid *g, int B, wm_precision prec, const void *q, const void *k, const void *v,
-                     const float *rpb, void *out, void *ws, hipStream_t s);
+                     const float *rpb, void *out, bool blocked_v, void *ws, hipStream_t s);
+bool ring_attention_applies(const wm_grid *g, int B, long ts);
 
 
 // Bytes of workspace a block of processor p needs for B states.

@@ -535,6 +535,38 @@ def test_block_rope_sharp_attention_discriminates(env, prec):
     p.close()
 
 
+@pytest.mark.parametrize("gi", [0, 1])
+def test_block_sharp_attention(env, gi):
+    """With N(0, 0.02) weights the softmax is nearly flat, so a block's
+    output hardly depends on q and k (it is close to the window mean of v):
+    a wrong q, k or key/value pairing can pass the flat tests.  Here the q
+    and k columns of W_qkv are scaled by 20 (scores with a spread of tens of
+    log2 units, most weight on a few keys).  Bounds on the increment x'' - x
+    against the oracle: FP32 1e-4 (measured 1.2e-6); BF16 3e-2 (measured
+    1.1-1.2e-2: bf16 rounding of q and k, 2^-9 relative, moves scores of
+    that size by ~0.1, i.e. weights by ~7%); FP8 0.3 (measured 0.17-0.18,
+    e4m3 q and k).  A q/k or k/v mix-up gives 0.2 and more in BF16."""
+    wm, torch, ctx = env
+    g = [S.CFG1, grid(8, 12, 24, C=512, heads=16, Kz=5, Ky=7, Kx=7)][gi]
+    x = S.latent_state(g, 1, 0)
+    params = S.processor_params(g, 1, 1).copy()
+    off = 0
+    for name, shape in S.block_param_layout(g):
+        n = int(np.prod(shape))
+        if name == "w_qkv":
+            params[off:off + n].reshape(shape)[:, :2 * g.C] *= 20.0 * (128 / g.C) ** 0.5
+        off += n
+    ref = O.block(x, S.split_block_params(g, params, 0), g)
+    for prec, tol in ((0, 1e-4), (1, 3e-2), (2, 0.3)):
+        p = wm.wm_processor_create(ctx, g, 1, 4, prec, params)
+        xd = torch.from_numpy(x).cuda()
+        wm.wm_processor_block(ctx, p, 0, 1, xd)
+        err = O.rel_l2(xd.cpu().numpy() - x, ref - x)
+        say(f"sharp block {g.Z}x{g.Y}x{g.X} C={g.C} prec {prec}: increment rel_l2 {err:.3e} (tol {tol})")
+        assert err <= tol
+        p.close()
+
+
 def test_block_width_1024_sampled(env):
     """The encoder/decoder width: one BF16 block at 8 x 90 x 180 with
     C=1024 (32 heads), window 5x7x7, sampled tokens."""
