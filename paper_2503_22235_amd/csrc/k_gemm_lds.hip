@@ -23,6 +23,7 @@
 // order (consecutive ids on one XCD share an activation tile in its L2).
 #include <algorithm>
 #include <cstdlib>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -203,18 +204,18 @@ __device__ __forceinline__ void mma_stage(const unsigned char *sb, const int *ao
     }
 }
 
-// Epilogue of the V projection (EPI_VT, swapped operands): acc[j][i]
+// Epilogue of a V tile of the QKV projection (swapped operands): acc[j][i]
 // holds tokens r0 + 16 i + 4 g + (0..3) (chunk rows) of V feature
-// f0 + 16 j + r16 (head f >> 5, channel f & 31); each lane stores its four tokens' values as 8 bytes of
+// f0 + 16 j + r16 (head f >> 5, channel f & 31; V bias `bias`); each lane stores its four tokens' values as 8 bytes of
 // the blocked layout (plus the wrapped copies near lon 0 and X).  Rows whose
 // four tokens leave a lat row (X or the state size not a multiple of 4)
 // are stored one by one.
 template <int TM, int TN>
-__device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, int M, int r0, int f0, const f32x4 (&acc)[TN][TM],
-                                            int g, int r16) {
+__device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, const float *bias, int M, int r0, int f0,
+                                            const f32x4 (&acc)[TN][TM], int g, int r16) {
     float bv[TN];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) bv[j] = ep.bias[f0 + 16 * j + r16];
+    for (int j = 0; j < TN; ++j) bv[j] = bias[f0 + 16 * j + r16];
     const int X = ep.vX, xp = ep.vxp, YX = ep.vY * ep.vX;
     const bool quad = (X & 3) == 0 && (ep.T & 3) == 0;
     bf16 *vt = (bf16 *)ep.vt;
@@ -339,11 +340,6 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
     };
 
     constexpr bool ZSTART = !FP8 && EPI != EPI_QKV_ROPE;
-    f32x4 acc[TN][TM];
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int i = 0; i < TM; ++i) acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // lane-constant fragment offsets inside a stage (swizzle depends on r16
     // only): bf16 k-step ks reads 16 bytes at k = 32ks + 8g; fp8 k-step ks
@@ -363,9 +359,18 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
 #pragma unroll
     for (int a = 0; a < AHEAD; ++a)
         if (a < S) issue(a, a);
-    // V projection into the blocked layout: swapped operands
-    constexpr bool SWAP = EPI == EPI_VT;
-    static_assert(!(SWAP && FP8), "blocked V comes from bf16 operands");
+
+    // The tiles of this workgroup.  SWAP (the V tiles of a bf16 QKV
+    // projection with ep.vt set; a workgroup's tiles are all V or none):
+    // swapped MFMA operands and the blocked-layout epilogue.  The two bodies
+    // are separate instantiations, so neither carries the other's registers.
+    auto body = [&](auto swap_tag) {
+    constexpr bool SWAP = decltype(swap_tag)::value;
+    f32x4 acc[TN][TM];
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int i = 0; i < TM; ++i) acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int t = 0; t < nn; ++t) {
         for (int kt = 0; kt < nk; ++kt) {
             const int st = t * nk + kt;
@@ -389,7 +394,13 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         const int n0 = (rw ? tn0 : tn0 + t) * BN;
         const int mt = rw ? m0 + t * BM : m0;    // first row of this tile
         if constexpr (SWAP) {
-            vt_epilogue<TM, TN>(ep, M, mt + wm * WM, n0 + wn * WN, acc, g, r16);
+            vt_epilogue<TM, TN>(ep, ep.bias + 2 * ep.C, M, mt + wm * WM, n0 - 2 * ep.C + wn * WN, acc, g, r16);
+            if constexpr (!ZSTART) {
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
             continue;
         }
         // a feature tile never straddles Q/K/V (C is a multiple of BN)
@@ -512,6 +523,14 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
             }
         }
     }
+    };
+    if constexpr (epi_qkv(EPI) && !FP8) {
+        if (ep.vt && tn0 * BN >= 2 * ep.C) {
+            body(std::true_type{});
+            return;
+        }
+    }
+    body(std::false_type{});
 #endif
 }
 
@@ -529,14 +548,12 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
     // LDS limit of the variants, set once per process (a local static's
     // initialisation is thread-safe; the server thread launches too)
     static const hipError_t attr_err = [] {
-        const void *fns[6] = {(const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8>,
+        const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8>,
                               (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8>,
-                              FP8 ? nullptr : (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_VT, false>};
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8>};
         for (const void *f : fns) {
-            if (!f) continue;
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
         }
@@ -584,10 +601,6 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
         case EPI_RESID:
             gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
-        case EPI_VT:
-            if constexpr (FP8) return hipErrorInvalidValue;
-            else gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_VT, false><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
-            break;
         default:
             gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
@@ -628,6 +641,13 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
     case 4: return launch_cfg<256, 128, 128, 3, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
     case 9: return launch_cfg<256, 128, 64, 3, 4, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
     default: break;
+    }
+    if (epi_qkv(epi) && ep.vt) {
+        // a workgroup's feature tiles must be all V or none: walk 2 when a
+        // part (C columns) holds an even number of tiles, else 1
+        const int bn = n256 ? 256 : 128, per_part = ep.C / bn;
+        if (n256) return launch_cfg<256, 256, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
+        return launch_cfg<128, 128, 128, 2, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
     }
     if (n256) {
         // N = 512 (the out-projection and MLP2 at C = 512): two row blocks of

@@ -21,8 +21,7 @@ enum EpiKind : int {
     EPI_GELU = 1,   // gelu(+bias) -> out [M][N]
     EPI_RESID = 2,  // resid[m][n] += acc + bias (float32 in place)
     EPI_STORE = 3,  // +bias -> out [M][N]
-    EPI_QKV_ROPE = 4, // EPI_QKV with q and k rotated (EpiArgs.rope)
-    EPI_VT = 5        // +bias -> EpiArgs.vt in the blocked V layout (bf16 LDS GEMM only)
+    EPI_QKV_ROPE = 4  // EPI_QKV with q and k rotated (EpiArgs.rope)
 };
 constexpr bool epi_qkv(int e) { return e == EPI_QKV || e == EPI_QKV_ROPE; }
 // Division of n < 2^31 by a fixed d >= 1 as a multiply-high and a shift
@@ -69,10 +68,12 @@ struct EpiArgs {
     // Set by the LDS GEMM launchers when they split M into row chunks: the
     // global row of the chunk's row 0 and the total row count.
     int row0, Mtot;
-    // EPI_VT: output feature f (head f >> 5, channel f & 31) goes to `vt`
-    // in the blocked layout of v_blocked_offset (grid vZ x vY x vX, vxp
-    // padded positions, vB states).  Divisors of a row index: tokens per
-    // state (T), per level, per lat row.
+    // EPI_QKV, bf16 LDS GEMM, vt set: V feature f (head f >> 5, channel
+    // f & 31) goes to `vt` in the blocked layout of v_blocked_offset (grid
+    // vZ x vY x vX, vxp padded positions, vB states) instead of the
+    // head-major scatter; the V rows of W are in natural order (Q and K rows
+    // permuted when perm is set).  Divisors of a row index: tokens per state
+    // (T), per level, per lat row.
     void *vt;
     int vB, vZ, vY, vX, vxp;
     UDiv dT, dYX, dX;

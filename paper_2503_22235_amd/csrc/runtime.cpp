@@ -132,34 +132,34 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
         ep.rZ = g.Z; ep.rY = g.Y; ep.rX = g.X;
         ep.T = T;
     }
-    // bf16: the Q and K columns (W rows permuted by perm_row, head-major
-    // output) and the V columns (W rows in natural order) are two launches;
-    // V goes to the blocked layout when the tiled attention reads it.
+    // bf16: W_qkv holds the Q and K rows permuted by perm_row and the V rows
+    // in natural order.  When the attention reads the blocked V layout, one
+    // launch writes Q and K head-major and V blocked (its V workgroups swap
+    // the MFMA operands); otherwise Q|K and V are two launches.
     auto qkv = [&]() -> hipError_t {
         const EpiKind kqk = p->rope_tab ? EPI_QKV_ROPE : EPI_QKV;
         if (!bf) return launch_gemm(act, w.w_qkv, M, 3 * C, C, false, kqk, ep, s);
         EpiArgs eqk = ep;
         eqk.perm = 1;
+        if (na.vt) {
+            eqk.vt = (void *)na.v;
+            eqk.vB = B; eqk.vZ = g.Z; eqk.vY = g.Y; eqk.vX = g.X; eqk.vxp = na.xp;
+            eqk.T = T;
+            eqk.dT = udiv_make((unsigned)T);
+            eqk.dYX = udiv_make((unsigned)(g.Y * g.X));
+            eqk.dX = udiv_make((unsigned)g.X);
+            return launch_gemm(act, w.w_qkv, M, 3 * C, C, true, kqk, eqk, s);
+        }
         hipError_t err = launch_gemm(act, w.w_qkv, M, 2 * C, C, true, kqk, eqk, s);
         if (err != hipSuccess) return err;
-        const void *wv = (const unsigned char *)w.w_qkv + (size_t)2 * C * C * 2;
         EpiArgs ev{};
         ev.bias = w.b_qkv + 2 * C;
-        if (na.vt) {
-            ev.vt = (void *)na.v;
-            ev.vB = B; ev.vZ = g.Z; ev.vY = g.Y; ev.vX = g.X; ev.vxp = na.xp;
-            ev.T = T;
-            ev.dT = udiv_make((unsigned)T);
-            ev.dYX = udiv_make((unsigned)(g.Y * g.X));
-            ev.dX = udiv_make((unsigned)g.X);
-            return launch_gemm(act, wv, M, C, C, true, EPI_VT, ev, s);
-        }
         ev.out = big;
         ev.C = C;
         ev.H = H;
         ev.qscale = 1.0f;
         ev.part0 = 2;
-        return launch_gemm(act, wv, M, C, C, true, EPI_QKV, ev, s);
+        return launch_gemm(act, (const unsigned char *)w.w_qkv + (size_t)2 * C * C * 2, M, C, C, true, EPI_QKV, ev, s);
     };
     WM_TIMED(PK_QKV, qkv(), "QKV")
 
