@@ -5,13 +5,15 @@
 //
 // A workgroup of WGM x WGN waves computes a BM x BN tile; each wave owns a
 // (BM/WGM) x (BN/WGN) sub-tile of 16x16x32 MFMA tiles.  The default for the
-// block's shapes is 256 x 256 with 8 waves (wave tile 64 x 128) and two
-// 64 KB stages, one workgroup per CU; 128 x 128 with 4 waves and two
-// workgroups per CU covers N not divisible by 256.  K advances in stages of
-// BKB bytes per row (64 bf16 or 128 e4m3 values for 128-byte rows).
-// Each stage is written straight from global memory into LDS by
-// buffer_load_dwordx4 ... lds (no register staging), issued STAGES-1
-// stages ahead.  A workgroup owns one token tile and walks one or more
+// block's shapes is 256 x 256 with 8 waves (wave tile 64 x 128), one
+// workgroup per CU; 128 x 128 with 4 waves and two workgroups per CU covers
+// N not divisible by 256.  K advances in stages of BKB bytes per row (64
+// bf16 or 128 e4m3 values for 128-byte rows).  Each stage is written
+// straight from global memory into LDS by buffer_load_dwordx4 ... lds (no
+// register staging): the activation tile and the weight tile through rings
+// of two slots each, one stage ahead (a three-slot activation ring, two
+// stages ahead, is a launch option).  A workgroup
+// owns one token tile and walks one or more
 // output-feature tiles; the stage stream runs on across tile boundaries, so
 // the next tile's first loads are in flight while the previous tile's
 // epilogue runs.  Rows of A past M come back as zeros from the buffer range
@@ -152,34 +154,22 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// Wait until at most `rem` (clipped to MAXN) later stages' loads are
-// outstanding: rem is the number of stages issued after the one needed.
-template <int MAXN, int LPW>
-__device__ __forceinline__ void wait_stages(int rem) {
-    if constexpr (MAXN == 0) {
-        wait_vmcnt<0>();
-    } else {
-        if (rem >= MAXN) wait_vmcnt<MAXN * LPW>();
-        else wait_stages<MAXN - 1, LPW>(rem);
-    }
-}
-
 // The MFMAs of one K stage for a wave's TM x TN tiles.  FIRST: the stage is
 // the tile's first, so its first k-step adds to zero instead of acc.
 // SWAP (bf16): the activation tile is the MFMA "A" operand, so a lane holds
 // four consecutive tokens of one output feature (the blocked V layout).
 template <bool FIRST, bool FP8, int TM, int TN, int KSTEPS, int BKB, bool SWAP = false>
-__device__ __forceinline__ void mma_stage(const unsigned char *sb, const int *aoff, const int *woff,
-                                          f32x4 (&acc)[TN][TM]) {
+__device__ __forceinline__ void mma_stage(const unsigned char *sa, const unsigned char *sw, const int *aoff,
+                                          const int *woff, f32x4 (&acc)[TN][TM]) {
     const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
         if constexpr (FP8) {
             long af[TM], wf[TN];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) af[i] = *(const long *)(sb + aoff[ks] + 16 * i * BKB);
+            for (int i = 0; i < TM; ++i) af[i] = *(const long *)(sa + aoff[ks] + 16 * i * BKB);
 #pragma unroll
-            for (int j = 0; j < TN; ++j) wf[j] = *(const long *)(sb + woff[ks] + 16 * j * BKB);
+            for (int j = 0; j < TN; ++j) wf[j] = *(const long *)(sw + woff[ks] + 16 * j * BKB);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -189,9 +179,9 @@ __device__ __forceinline__ void mma_stage(const unsigned char *sb, const int *ao
         } else {
             bf16x8 af[TM], wf[TN];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sb + aoff[ks] + 16 * i * BKB);
+            for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sa + aoff[ks] + 16 * i * BKB);
 #pragma unroll
-            for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sb + woff[ks] + 16 * j * BKB);
+            for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sw + woff[ks] + 16 * j * BKB);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -266,22 +256,27 @@ __device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, const float *bias
 // FP8: operands are e4m3 bytes (128 k-values per 128-byte stage, MFMA
 // 16x16x32 fp8 with 8-byte fragments); the epilogue dequantizes per row.
 // WGM x WGN waves tile the BM x BN output; OCC workgroups share a CU.
-template <int BM, int BN, int BKB, int STAGES, int WGM, int WGN, int OCC, int EPI, bool FP8>
+// The activation tile of each K stage streams through a ring of SA slots
+// (SA - 1 stages ahead: it comes from HBM) and the weight tile through a
+// ring of SW slots (SW - 1 ahead: it stays in L2); SW = 2, SA = 2 or 3.
+template <int BM, int BN, int BKB, int SA, int SW, int WGM, int WGN, int OCC, int EPI, bool FP8>
 __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const void *__restrict__ A, const void *__restrict__ W,
                                                          int M, int N, int K, EpiArgs ep, int tpw, int rw) {
 #if defined(__HIP_DEVICE_COMPILE__)   // LDS-address-space builtins exist only in the device pass
     constexpr int NW = WGM * WGN;
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TM = WM / 16, TN = WN / 16;
-    constexpr int ROWS = BM + BN;                  // LDS rows per stage
-    constexpr int STAGE_BYTES = ROWS * BKB;
+    constexpr int ABYTES = BM * BKB, WBYTES = BN * BKB;   // one slot of each ring
     constexpr int CPR = BKB / 16;                  // 16-byte chunks per LDS row
     constexpr int RPI = 64 / CPR;                  // rows one load instruction fills
-    constexpr int LPW = ROWS / RPI / NW;           // load instructions per wave per stage
+    constexpr int LPA = BM / RPI / NW;             // activation load instructions per wave per stage
+    constexpr int LPB = BN / RPI / NW;             // weight load instructions per wave per stage
     static_assert(BKB == 128 || BKB == 64, "stage row bytes");
-    static_assert(ROWS % (RPI * NW) == 0 && BM % (RPI * NW) == 0, "rows per stage must split over the waves");
+    static_assert(BM % (RPI * NW) == 0 && BN % (RPI * NW) == 0, "rows per stage must split over the waves");
     static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile");
+    static_assert(SW == 2 && (SA == 2 || SA == 3), "ring depths");
     extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char *const aring = smem, *const wring = smem + SA * ABYTES;
 
     // A workgroup computes nn tiles: feature tiles tn0 .. tn0+nn-1 of row
     // block m0 (rw == 0), or row blocks m0, m0+BM, .. of feature tile tn0
@@ -308,35 +303,40 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
     const __amdgpu_buffer_rsrc_t ars = make_rsrc(A, (unsigned)M * Kb);
     const __amdgpu_buffer_rsrc_t wrs = make_rsrc(W, (unsigned)N * Kb);
 
-    // per-lane global byte offsets of this wave's load instructions
-    // Instruction i of wave w fills LDS rows RPI(w + NW i) .. +RPI-1; since BM
-    // is a multiple of RPI NW, rows below BM (activation rows) are exactly
-    // i < BM/(RPI NW).
-    unsigned voff[LPW];
+    // per-lane global byte offsets of this wave's load instructions:
+    // instruction i of wave w fills rows RPI (w + NW i) .. +RPI-1 of a slot
+    unsigned voa[LPA], vob[LPB];
 #pragma unroll
-    for (int i = 0; i < LPW; ++i) {
+    for (int i = 0; i < LPA; ++i) {
         const int row = RPI * (wave + NW * i) + lane / CPR;
-        const int lc = (lane % CPR) ^ swz<BKB>(row);
-        voff[i] = i < BM / (RPI * NW) ? (unsigned)(m0 + row) * Kb + lc * 16
-                              : (unsigned)(tn0 * BN + row - BM) * Kb + lc * 16;
+        voa[i] = (unsigned)(m0 + row) * Kb + (((lane % CPR) ^ swz<BKB>(row)) << 4);
+    }
+#pragma unroll
+    for (int i = 0; i < LPB; ++i) {
+        const int row = RPI * (wave + NW * i) + lane / CPR;
+        vob[i] = (unsigned)(tn0 * BN + row) * Kb + (((lane % CPR) ^ swz<BKB>(row)) << 4);
     }
     const int nk = K / (FP8 ? BKB : BKB / 2);
-    // stage s of the stream = k-stage (s % nk) of feature tile (s / nk)
-    auto issue = [&](int s, int stage) {
+    // stage s of the stream = k-stage (s % nk) of tile (s / nk)
+    auto issue_a = [&](int s) {
         const int t = s / nk, kt = s - t * nk;
-        unsigned char *sbase = smem + stage * STAGE_BYTES;
-        const unsigned wsoff = (unsigned)t * wstep + kt * BKB;
+        unsigned char *sbase = aring + (s % SA) * ABYTES;
         // the row advance goes into the vector offset: rows past M must fail
         // the buffer range check and read zero
         const unsigned aadv = (unsigned)t * astep;
 #pragma unroll
-        for (int i = 0; i < LPW; ++i) {
-            lds_void *dst = (lds_void *)(sbase + RPI * (wave + NW * i) * BKB);
-            if (i < BM / (RPI * NW))
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(ars, dst, 16, voff[i] + aadv, kt * BKB, 0, 0);
-            else
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, dst, 16, voff[i], wsoff, 0, 0);
-        }
+        for (int i = 0; i < LPA; ++i)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ars, (lds_void *)(sbase + RPI * (wave + NW * i) * BKB), 16,
+                                                     voa[i] + aadv, kt * BKB, 0, 0);
+    };
+    auto issue_w = [&](int s) {
+        const int t = s / nk, kt = s - t * nk;
+        unsigned char *sbase = wring + (s % SW) * WBYTES;
+        const unsigned wsoff = (unsigned)t * wstep + kt * BKB;
+#pragma unroll
+        for (int i = 0; i < LPB; ++i)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(wrs, (lds_void *)(sbase + RPI * (wave + NW * i) * BKB), 16,
+                                                     vob[i], wsoff, 0, 0);
     };
 
     constexpr bool ZSTART = !FP8 && EPI != EPI_QKV_ROPE;
@@ -351,14 +351,16 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         const int pc = FP8 ? ((((2 * ks + (g >> 1)) ^ swz<BKB>(r16)) << 4) + 8 * (g & 1))
                            : (((4 * ks + g) ^ swz<BKB>(r16)) << 4);
         aoff[ks] = (wm * WM + r16) * BKB + pc;
-        woff[ks] = (BM + wn * WN + r16) * BKB + pc;
+        woff[ks] = (wn * WN + r16) * BKB + pc;
     }
 
+    // Issue order: A(0), W(0), A(1) (SA = 3), then in iteration st W(st+1)
+    // and A(st+SA-1).  So when iteration st waits, only A(st+1) (SA = 3) was
+    // issued after W(st), and A(st) before it.
     const int S = nn * nk;
-    constexpr int AHEAD = STAGES - 1;                // stages in flight ahead of the one in use
-#pragma unroll
-    for (int a = 0; a < AHEAD; ++a)
-        if (a < S) issue(a, a);
+    issue_a(0);
+    issue_w(0);
+    if (SA == 3 && S > 1) issue_a(1);
 
     // The tiles of this workgroup.  SWAP (the V tiles of a bf16 QKV
     // projection with ep.vt set; a workgroup's tiles are all V or none):
@@ -374,22 +376,23 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
     for (int t = 0; t < nn; ++t) {
         for (int kt = 0; kt < nk; ++kt) {
             const int st = t * nk + kt;
-            // This wave's loads of stage st have landed once at most the loads
-            // of the stages issued after it (up to AHEAD - 1 of them) are
-            // outstanding; the barrier then makes all waves' parts of stage st
-            // visible and frees the stage read in iteration st - 1.  (A bare
-            // s_barrier: __syncthreads() would also drain the stages still in
-            // flight.)
-            wait_stages<AHEAD - 1, LPW>(min(S - 1 - st, AHEAD - 1));
+            // This wave's loads of stage st have landed once at most the
+            // loads of A(st+1) are outstanding; the barrier then makes all
+            // waves' parts of stage st visible and frees the slots read in
+            // iteration st - 1.  (A bare s_barrier: __syncthreads() would
+            // also drain the loads still in flight.)
+            if (SA == 3 && st + 1 < S) wait_vmcnt<LPA>();
+            else wait_vmcnt<0>();
             __builtin_amdgcn_s_barrier();
-            if (st + AHEAD < S) issue(st + AHEAD, (st + AHEAD) % STAGES);
-            const unsigned char *sb = smem + (st % STAGES) * STAGE_BYTES;
+            if (st + 1 < S) issue_w(st + 1);
+            if (st + SA - 1 < S) issue_a(st + SA - 1);
+            const unsigned char *sbA = aring + (st % SA) * ABYTES, *sbW = wring + (st % SW) * WBYTES;
             // ZSTART: a tile's first k-step starts its accumulators from an
             // inline zero operand instead of registers cleared in the previous
             // epilogue (not for the FP8 and rotary variants, whose extra
             // registers would spill with a second copy of the stage code)
-            if (ZSTART && kt == 0) mma_stage<ZSTART, FP8, TM, TN, KSTEPS, BKB, SWAP>(sb, aoff, woff, acc);
-            else mma_stage<false, FP8, TM, TN, KSTEPS, BKB, SWAP>(sb, aoff, woff, acc);
+            if (ZSTART && kt == 0) mma_stage<ZSTART, FP8, TM, TN, KSTEPS, BKB, SWAP>(sbA, sbW, aoff, woff, acc);
+            else mma_stage<false, FP8, TM, TN, KSTEPS, BKB, SWAP>(sbA, sbW, aoff, woff, acc);
         }
         const int n0 = (rw ? tn0 : tn0 + t) * BN;
         const int mt = rw ? m0 + t * BM : m0;    // first row of this tile
@@ -539,20 +542,20 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
 // (measured); other N of 1536 or more take 2, smaller N take 1.
 inline int wide_tpw(int N) { return N == 1536 ? 3 : (N == 2048 ? 4 : (N >= 1536 ? 2 : 1)); }
 
-template <int BM, int BN, int BKB, int STAGES, int WGM, int WGN, int OCC, bool FP8>
+template <int BM, int BN, int BKB, int SA, int SW, int WGM, int WGN, int OCC, bool FP8>
 hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                       hipStream_t stream, int tpw_default = 1, int rw_default = 0) {
-    constexpr size_t lds = (size_t)STAGES * (BM + BN) * BKB;
+    constexpr size_t lds = (size_t)SA * BM * BKB + (size_t)SW * BN * BKB;
     static_assert(lds * OCC <= 160 * 1024, "LDS per CU");
     constexpr int NTH = 64 * WGM * WGN;
     // LDS limit of the variants, set once per process (a local static's
     // initialisation is thread-safe; the server thread launches too)
     static const hipError_t attr_err = [] {
-        const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8>};
+        const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_QKV, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_GELU, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_RESID, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_STORE, FP8>};
         for (const void *f : fns) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
@@ -590,25 +593,41 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
         const int grid = ((total + 7) >> 3) << 3;
         switch (epi) {
         case EPI_QKV:
-            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_QKV, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         case EPI_QKV_ROPE:
-            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_QKV_ROPE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_QKV_ROPE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         case EPI_GELU:
-            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_GELU, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_GELU, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         case EPI_RESID:
-            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_RESID, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_RESID, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         default:
-            gemm_lds_kernel<BM, BN, BKB, STAGES, WGM, WGN, OCC, EPI_STORE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_STORE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         }
         const hipError_t err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
+}
+
+// Depth of the activation ring: 2 (one stage ahead), or 3 with
+// WM_GEMM_SA=3 (two ahead; measured no faster on the block's shapes, whose
+// main loop is bound by LDS traffic -- fragment reads plus the stage writes --
+// rather than by load latency).
+template <int BM, int BN, int BKB, int WGM, int WGN, int OCC, bool FP8>
+hipError_t launch_sa(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
+                     hipStream_t stream, int tpw_default = 1, int rw_default = 0) {
+    static const int sa = [] {
+        const char *v = getenv("WM_GEMM_SA");
+        return v && atoi(v) == 3 ? 3 : 2;
+    }();
+    if (sa == 3)
+        return launch_cfg<BM, BN, BKB, 3, 2, WGM, WGN, OCC, FP8>(A, W, M, N, K, epi, ep, stream, tpw_default, rw_default);
+    return launch_cfg<BM, BN, BKB, 2, 2, WGM, WGN, OCC, FP8>(A, W, M, N, K, epi, ep, stream, tpw_default, rw_default);
 }
 
 }  // namespace glds
@@ -636,27 +655,27 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
     // (a QKV feature tile must not straddle two of Q, K and V: BN divides C)
     const bool n256 = N % 256 == 0 && (!epi_qkv(epi) || ep.C % 256 == 0);
     switch (cfg) {
-    case 0: return launch_cfg<128, 128, 128, 2, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
-    case 3: return launch_cfg<256, 128, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
-    case 4: return launch_cfg<256, 128, 128, 3, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
-    case 9: return launch_cfg<256, 128, 64, 3, 4, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
+    case 0: return launch_sa<128, 128, 128, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
+    case 3: return launch_cfg<256, 128, 128, 2, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
+    case 4: return launch_cfg<256, 128, 128, 3, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
+    case 9: return launch_cfg<256, 128, 64, 3, 2, 4, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
     default: break;
     }
     if (epi_qkv(epi) && ep.vt) {
         // a workgroup's feature tiles must be all V or none: walk 2 when a
         // part (C columns) holds an even number of tiles, else 1
         const int bn = n256 ? 256 : 128, per_part = ep.C / bn;
-        if (n256) return launch_cfg<256, 256, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
-        return launch_cfg<128, 128, 128, 2, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
+        if (n256) return launch_sa<256, 256, 128, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
+        return launch_sa<128, 128, 128, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
     }
     if (n256) {
         // N = 512 (the out-projection and MLP2 at C = 512): two row blocks of
         // one feature tile per workgroup (measured 2-3% faster than one tile
         // per workgroup; walking feature tiles is faster for wide N)
-        if (N == 512) return launch_cfg<256, 256, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, 2, 1);
-        return launch_cfg<256, 256, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, wide_tpw(N), 0);
+        if (N == 512) return launch_sa<256, 256, 128, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, 2, 1);
+        return launch_sa<256, 256, 128, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, wide_tpw(N), 0);
     }
-    return launch_cfg<128, 128, 128, 2, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
+    return launch_sa<128, 128, 128, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
 }
 
 hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
@@ -669,10 +688,10 @@ hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, Ep
     }();
     if (N % 256 == 0 && (!epi_qkv(epi) || ep.C % 256 == 0) && cfg != 0) {
         // N = 512 (MLP2 at C = 512): row walk, as in launch_gemm_lds
-        if (N == 512) return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, 2, 1);
-        return launch_cfg<256, 256, 128, 2, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, wide_tpw(N), 0);
+        if (N == 512) return launch_sa<256, 256, 128, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, 2, 1);
+        return launch_sa<256, 256, 128, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, wide_tpw(N), 0);
     }
-    return launch_cfg<128, 128, 128, 2, 2, 2, 2, true>(A, W, M, N, K, epi, ep, stream);
+    return launch_sa<128, 128, 128, 2, 2, 2, true>(A, W, M, N, K, epi, ep, stream);
 }
 
 }  // namespace wm
