@@ -165,17 +165,28 @@ __device__ __forceinline__ void mma_stage(const unsigned char *sa, const unsigne
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
         if constexpr (FP8) {
-            long af[TM], wf[TN];
+            // gfx950 16x16x128 f8f6f4 MFMA (e4m3 x e4m3): a lane holds 32
+            // k-values of its row for both operands, the k chunk 32 g .. 32 g
+            // + 31 of the stage read as two 16-byte pieces (aoff[2 ks],
+            // aoff[2 ks + 1]); both operands use the same k assignment, which
+            // is all a contraction over k needs.
+            i32x8 af[TM];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) af[i] = *(const long *)(sa + aoff[ks] + 16 * i * BKB);
+            for (int i = 0; i < TM; ++i) {
+                const uint4 lo = *(const uint4 *)(sa + aoff[2 * ks] + 16 * i * BKB);
+                const uint4 hi = *(const uint4 *)(sa + aoff[2 * ks + 1] + 16 * i * BKB);
+                af[i] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+            }
 #pragma unroll
-            for (int j = 0; j < TN; ++j) wf[j] = *(const long *)(sw + woff[ks] + 16 * j * BKB);
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
+            for (int j = 0; j < TN; ++j) {
+                const uint4 lo = *(const uint4 *)(sw + woff[2 * ks] + 16 * j * BKB);
+                const uint4 hi = *(const uint4 *)(sw + woff[2 * ks + 1] + 16 * j * BKB);
+                const i32x8 wf = {(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
-                    acc[j][i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(wf[j], af[i], FIRST && ks == 0 ? zero : acc[j][i],
-                                                                           0, 0, 0);
+                    acc[j][i] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                        wf, af[i], FIRST && ks == 0 ? zero : acc[j][i], 0, 0, 0, 0, 0, 0);
+            }
         } else {
             bf16x8 af[TM], wf[TN];
 #pragma unroll
@@ -254,7 +265,7 @@ __device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, const float *bias
 }
 
 // FP8: operands are e4m3 bytes (128 k-values per 128-byte stage, MFMA
-// 16x16x32 fp8 with 8-byte fragments); the epilogue dequantizes per row.
+// 16x16x128 f8f6f4, one k-step per stage); the epilogue dequantizes per row.
 // WGM x WGN waves tile the BM x BN output; OCC workgroups share a CU.
 // The activation tile of each K stage streams through a ring of SA slots
 // (SA - 1 stages ahead: it comes from HBM) and the weight tile through a
@@ -344,14 +355,18 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
     // lane-constant fragment offsets inside a stage (swizzle depends on r16
     // only): bf16 k-step ks reads 16 bytes at k = 32ks + 8g; fp8 k-step ks
     // reads 8 bytes at k = 32ks + 8g.
-    constexpr int KSTEPS = FP8 ? BKB / 32 : BKB / 64;
-    int aoff[KSTEPS], woff[KSTEPS];
+    // fp8: one 16x16x128 k-step per 128-byte stage; a lane reads chunks
+    // 2g and 2g + 1 (k = 32 g .. 32 g + 31) of its row.
+    constexpr int KSTEPS = FP8 ? BKB / 128 : BKB / 64;
+    constexpr int NOFF = FP8 ? 2 * KSTEPS : KSTEPS;
+    static_assert(!FP8 || BKB == 128, "fp8 stages hold one 128-k MFMA step");
+    int aoff[NOFF], woff[NOFF];
 #pragma unroll
-    for (int ks = 0; ks < KSTEPS; ++ks) {
-        const int pc = FP8 ? ((((2 * ks + (g >> 1)) ^ swz<BKB>(r16)) << 4) + 8 * (g & 1))
-                           : (((4 * ks + g) ^ swz<BKB>(r16)) << 4);
-        aoff[ks] = (wm * WM + r16) * BKB + pc;
-        woff[ks] = (wn * WN + r16) * BKB + pc;
+    for (int o = 0; o < NOFF; ++o) {
+        const int pc = FP8 ? (((8 * (o >> 1) + 2 * g + (o & 1)) ^ swz<BKB>(r16)) << 4)
+                           : (((4 * o + g) ^ swz<BKB>(r16)) << 4);
+        aoff[o] = (wm * WM + r16) * BKB + pc;
+        woff[o] = (wn * WN + r16) * BKB + pc;
     }
 
     // Issue order: A(0), W(0), A(1) (SA = 3), then in iteration st W(st+1)
