@@ -363,7 +363,7 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
     const size_t esz = prec == WM_F32 ? 4 : 2;
     const size_t esz_big = fp8 ? 1 : esz;
     // Device image per block: float32 vectors, then the four transposed weights.
-    const size_t nvec = 2 * C + 3 * C + nrpb + C + 2 * C + F + C;
+    const size_t nvec = 2 * C + 3 * C + nrpb + C + 2 * C + F + C + 2;
     const size_t nw_bytes = ((size_t)3 * C * C + (size_t)F * C * 2) * esz_big + (size_t)C * C * esz + 4 * 256;
     auto align = [](size_t b) { return (b + 255) & ~(size_t)255; };
     // BF16: room for the tiled attention kernel's prepared bias table
@@ -442,6 +442,22 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
         put_vec(ln2_b, C, 1.f, &bw.ln2_b);
         put_vec(b_1, F, 1.f, &bw.b_1);
         put_vec(b_2, C, 1.f, &bw.b_2);
+        if (fp8) {
+            // static LayerNorm-output amax: |gamma_c| sqrt(C - 1) + |beta_c| bounds channel c
+            auto ln_bound = [&](const float *gm, const float *bt) {
+                double m = 0.0;
+                for (int c = 0; c < C; ++c)
+                    m = std::max(m, std::fabs((double)gm[c]) * std::sqrt((double)(C - 1)) + std::fabs((double)bt[c]));
+                return (float)m;
+            };
+            const float a2[2] = {ln_bound(ln1_g, ln1_b), ln_bound(ln2_g, ln2_b)};
+            const float *d2 = nullptr;
+            put_vec(a2, 2, 1.f, &d2);
+            bw.ln1_amax = d2;
+            bw.ln2_amax = d2 + 1;
+            bw.ln1_amax_h = a2[0];
+            bw.ln2_amax_h = a2[1];
+        }
         // QKV and MLP1 rows permuted (their epilogues store 8 features per
         // lane); the residual GEMMs keep the natural order
         // (bf16: the V rows of W_qkv keep their order; the V tiles of the

@@ -185,7 +185,27 @@ hipError_t ln_fp8(const float *x, const float *g, const float *b, int M, int T, 
     return hipGetLastError();
 }
 
+template <int VPT>
+hipError_t ln_fp8_static(const float *x, const float *g, const float *b, int M, float eps, const float *amax,
+                         unsigned char *out, hipStream_t s) {
+    // one scale for every row: the quantization pass alone (rows / M == 0)
+    ln_quant_kernel<VPT><<<(M + 3) / 4, 256, 0, s>>>(x, g, b, M, M, eps, amax, out);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_layernorm_fp8_static(const float *x, const float *gamma, const float *beta, int M, int C,
+                                       float eps, const float *amax, unsigned char *out, hipStream_t stream) {
+    if (M <= 0) return hipSuccess;
+    switch (C) {
+    case 128: return ln_fp8_static<2>(x, gamma, beta, M, eps, amax, out, stream);
+    case 256: return ln_fp8_static<4>(x, gamma, beta, M, eps, amax, out, stream);
+    case 512: return ln_fp8_static<8>(x, gamma, beta, M, eps, amax, out, stream);
+    case 1024: return ln_fp8_static<16>(x, gamma, beta, M, eps, amax, out, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_layernorm_fp8(const float *x, const float *gamma, const float *beta, int M, int C, int T,
                                 float eps, unsigned *amax, unsigned char *out, hipStream_t stream) {

@@ -133,6 +133,10 @@ hipError_t launch_amax_fold(unsigned *amax, int n, hipStream_t stream);
 // amax[state], which the caller zeroes), then LN + quantize.
 hipError_t launch_layernorm_fp8(const float *x, const float *gamma, const float *beta, int M, int C, int T,
                                 float eps, unsigned *amax, unsigned char *out, hipStream_t stream);
+// LayerNorm + quantize with one static amax (device float at `amax`) for
+// every row: a single pass.
+hipError_t launch_layernorm_fp8_static(const float *x, const float *gamma, const float *beta, int M, int C,
+                                       float eps, const float *amax, unsigned char *out, hipStream_t stream);
 // bf16 rows [M][F] -> e4m3 with each row's state scale (F % 8 == 0)
 hipError_t launch_quant_rows(const void *in_bf16, int M, int F, int T, const float *amax,
                              unsigned char *out, hipStream_t stream);

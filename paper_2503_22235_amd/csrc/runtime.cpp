@@ -203,7 +203,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     unsigned char *h8 = (unsigned char *)(obuf + al256((size_t)M * C * 2));
     float *tbl_ws = (float *)((char *)h8 + al256((size_t)M * F));
     unsigned *amax = (unsigned *)((char *)tbl_ws + (size_t)B * H * NAT_TBL_WS_FLOATS * 4);
-    unsigned *amax_u = amax, *amax_qkv = amax + B, *amax_w = amax + 4 * B, *amax_h = amax + 5 * B;
+    unsigned *amax_qkv = amax + B, *amax_h = amax + 5 * B;
     hipError_t e;
     int rc;
 #define WM_TIMED(kind, call, what)                                  \
@@ -214,14 +214,14 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     if (!fp8_attention_applies(&g, B, 32)) return fail(WM_EINVAL, "no e4m3 attention kernel for this grid and batch");
     if ((e = launch_zero_u32(amax, (size_t)AMAX_SHARDS * AMAX_STRIDE, s)) != hipSuccess)
         return hip_fail(e, "amax reset");
-    WM_TIMED(PK_LN1, launch_layernorm_fp8(x, w.ln1_g, w.ln1_b, M, C, (int)T, 1e-5f, amax_u, act8, s), "LN1")
+    WM_TIMED(PK_LN1, launch_layernorm_fp8_static(x, w.ln1_g, w.ln1_b, M, C, 1e-5f, w.ln1_amax, act8, s), "LN1")
     EpiArgs ep{};
     ep.bias = w.b_qkv;
     ep.out = big;
     ep.C = C;
     ep.H = H;
     ep.qscale = LOG2E / std::sqrt(32.0f);
-    ep.a_amax = (const float *)amax_u;
+    ep.a_dequant = w.ln1_amax_h / 448.0f;   // static scale of the LN1 codes
     ep.w_dequant = w.dq_qkv;
     ep.T = T;
     ep.out_amax = amax_qkv;
@@ -257,11 +257,11 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     er.bias = w.b_o;
     er.resid = x;
     WM_TIMED(PK_PROJ, launch_gemm(obuf, w.w_o, M, C, C, true, EPI_RESID, er, s), "proj")
-    WM_TIMED(PK_LN2, launch_layernorm_fp8(x, w.ln2_g, w.ln2_b, M, C, (int)T, 1e-5f, amax_w, act8, s), "LN2")
+    WM_TIMED(PK_LN2, launch_layernorm_fp8_static(x, w.ln2_g, w.ln2_b, M, C, 1e-5f, w.ln2_amax, act8, s), "LN2")
     EpiArgs eg{};
     eg.bias = w.b_1;
     eg.out = big;
-    eg.a_amax = (const float *)amax_w;
+    eg.a_dequant = w.ln2_amax_h / 448.0f;   // static scale of the LN2 codes
     eg.w_dequant = w.dq_1;
     eg.T = T;
     eg.out_amax = amax_h;

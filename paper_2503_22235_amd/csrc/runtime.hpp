@@ -18,6 +18,12 @@ struct BlockWeights {
     // FP8 processors: w_qkv, w_1, w_2 hold e4m3 codes with these per-tensor
     // dequantization scales (amax / 448); w_o stays bfloat16.
     float dq_qkv = 1.f, dq_1 = 1.f, dq_2 = 1.f;
+    // FP8 processors: static amax of each LayerNorm output (device float and
+    // its host copy): a LayerNorm output is bounded by
+    // max_c |gamma_c| sqrt(C - 1) + |beta_c| (the normalized values of a row
+    // have mean 0 and mean square 1, so none exceeds sqrt(C - 1)).
+    const float *ln1_amax = nullptr, *ln2_amax = nullptr;
+    float ln1_amax_h = 0.f, ln2_amax_h = 0.f;
     // BF16 processors: the tiled attention kernel's bias table of this
     // block, prepared once at creation (null: prepared per launch)
     float *nat_tbl = nullptr;
