@@ -782,6 +782,376 @@ __global__ void nat_bias_prep_fp8(NatArgs p) {
     p.tbl_ws[e] = v;
 }
 
+// ---------------------------------------------------------------------------
+// FP8 level-ring kernel (the FP8 block path): the arithmetic of
+// nat_tile_fp8_kernel (e4m3 QK and PV on 16x16x32 fp8 MFMA, scores in units
+// of c = s_q s_k, per-(state, head) bias table divided by c, e4m3 softmax
+// weights with the static scale 1) on the tiling and level streaming of
+// nat_ring_kernel.  K and V arrive already quantized (kv8 pass): K as e4m3
+// rows of 32 bytes per token, V in the blocked layout with byte elements.
+// A level is 10 lat rows of K (16 tokens x 32 bytes, the 16-byte halves of
+// token c in row R swapped when bit 1 of R is set, against bank conflicts)
+// and 10 of V (512 bytes), 10 KB; two slots alternate.  Reference: each
+// query's own score; the weights are exp2(c (s - m)), and if a score
+// exceeds m by more than TAU / c (a weight above 2^TAU, outside what the
+// e4m3 weights hold with the static scale) the workgroup finds the exact
+// maxima and runs the walk again.
+constexpr int RING8_ROWB = 512;                        // bytes per K or V row of a level
+constexpr int RING8_SLOT = 2 * RING_ROWS * RING8_ROWB;
+
+template <int BYTE>
+__device__ __forceinline__ float e4m3_f32(unsigned w) {
+    return __builtin_amdgcn_cvt_f32_fp8((int)w, BYTE);
+}
+// sum over the 4 bytes of a and b (e4m3 codes) of a_i b_i, added to s
+__device__ __forceinline__ float e4m3_dot4(unsigned a, unsigned b, float s) {
+    s = fmaf(e4m3_f32<0>(a), e4m3_f32<0>(b), s);
+    s = fmaf(e4m3_f32<1>(a), e4m3_f32<1>(b), s);
+    s = fmaf(e4m3_f32<2>(a), e4m3_f32<2>(b), s);
+    return fmaf(e4m3_f32<3>(a), e4m3_f32<3>(b), s);
+}
+
+template <int KZ, int KY, int KX>
+__global__ __launch_bounds__(256, 3) void nat_ring_fp8_kernel(NatArgs p, TileDiv dm) {
+    constexpr int RX = (KX - 1) / 2;
+    constexpr int BY = 2 * KY - 1;
+    constexpr int TBL = (2 * KZ - 1) * BY * XT;
+    constexpr int SX = 4 - RX;
+    static_assert(2 + KX - 1 <= 8 && 2 + KY - 1 <= 8, "window too large for the 8-wide group halo");
+    static_assert(TY + KY - 1 <= RING_ROWS, "lat halo rows per level");
+    constexpr int TBLP = tbl_padded<KZ, KY, KX>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *tbl = (float *)smem;
+    unsigned char *ring = smem + TBLP * 4;
+
+    const int ntz = (p.Z + TZ - 1) / TZ, nty = (p.Y + TY - 1) / TY, ntx = (p.X + TX - 1) / TX;
+    const int ntiles = ntz * nty * ntx;
+    const int total = ntiles * p.H * p.B;
+    const int per = (total + 7) >> 3;
+    const int L = blockIdx.x;
+    const int id = (L & 7) * per + (L >> 3);
+    if (id >= total) return;
+    unsigned t = (unsigned)id, q;
+    q = mdiv(t, dm.mx); const int tx = (int)(t - q * (unsigned)ntx); t = q;
+    q = mdiv(t, dm.my); const int ty = (int)(t - q * (unsigned)nty); t = q;
+    q = mdiv(t, dm.mz); const int tz = (int)(t - q * (unsigned)ntz); t = q;
+    q = mdiv(t, dm.mh); const int h = (int)(t - q * (unsigned)p.H);
+    const int b = (int)q;
+    const int z0 = tz * TZ, y0 = ty * TY;
+    const int x0 = tx * TX - SX;
+    const int hx0 = tx * TX - 4;
+
+    int zlo, zn, ylo, yn;
+    clamp_range(z0, TZ, p.Z, KZ, zlo, zn);
+    clamp_range(y0, TY, p.Y, KY, ylo, yn);
+
+    const unsigned char *k8 = (const unsigned char *)p.k + (size_t)b * p.bs + (size_t)h * p.hs;
+    const bf16 *qb = (const bf16 *)p.q + (size_t)b * p.bs + (size_t)h * p.hs;
+    const float aq = p.amax[(size_t)b * p.amax_stride], ak = p.amax[(size_t)b * p.amax_stride + 1],
+                av = p.amax[(size_t)b * p.amax_stride + 2];
+    const float c = dq_scale(aq) * dq_scale(ak) * p.qscale;     // score unit, log2 domain
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    // ---- level staging: instruction u = wave + 4 k (< 10) moves rows 2u, 2u+1
+    // of K (u < 5) or of V (u >= 5); rows past the halo repeat its last lat row
+    const unsigned tsb = (unsigned)p.ts;                // K token stride, bytes
+    const __amdgpu_buffer_rsrc_t krs = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(k8), 0, 0x7ffffffe, 0x00020000);
+    const size_t plane = (size_t)p.Z * p.Y * p.xp * 32;
+    const unsigned char *vp = (const unsigned char *)p.v + ((size_t)h * p.B + b) * plane;
+    const __amdgpu_buffer_rsrc_t vrs = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(vp), 0, (unsigned)plane, 0x00020000);
+    const int lrow = lane >> 5;                        // which of the instruction's two rows
+    unsigned kcol[2];
+    {
+        const int cc = (lane >> 1) & 15, hq = lane & 1;
+        int xk = hx0 + cc;
+        xk = xk < 0 ? xk + p.X : (xk >= p.X ? xk - p.X : xk);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {                  // K instructions of this wave: u = wave + 4 k
+            const int r = 2 * (wave + 4 * k) + lrow;
+            kcol[k] = (unsigned)xk * tsb + 16u * (unsigned)(hq ^ ((r >> 1) & 1));
+        }
+    }
+    const unsigned vcol = 256u * (unsigned)tx + 16u * (unsigned)(lane & 31);
+    const unsigned rowb = (unsigned)p.xp * 32u;
+    auto stage = [&](int hz, int slot) {
+        unsigned char *dst = ring + slot * RING8_SLOT;
+        const unsigned zr = (unsigned)(zlo + hz) * (unsigned)p.Y;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int u = wave + 4 * k;
+            if (u < 5) {
+                const int r = 2 * u + lrow;
+                const unsigned yy = (unsigned)min(ylo + r, ylo + yn - 1);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(krs, (lds_void *)(dst + 2 * u * RING8_ROWB), 16,
+                                                         (zr + yy) * (unsigned)p.X * tsb + kcol[k < 2 ? k : 0], 0, 0, 0);
+            } else if (u < 10) {
+                const int r = 2 * (u - 5) + lrow;
+                const unsigned yy = (unsigned)min(ylo + r, ylo + yn - 1);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(vrs, (lds_void *)(dst + (RING_ROWS + 2 * (u - 5)) * RING8_ROWB),
+                                                         16, (zr + yy) * rowb + vcol, 0, 0, 0);
+            }
+        }
+    };
+    stage(0, 0);
+    {
+        const uint4 *src = (const uint4 *)(p.tbl_ws + ((size_t)b * p.H + h) * TBLP);
+        for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
+    }
+
+    const int g = lane >> 4, r16 = lane & 15;
+    const int y0g = y0 + 2 * (wave & 1);
+    const int gxa = 2 * (wave >> 1);
+    const int zq = z0 + (r16 >> 2), yq = y0g + ((r16 >> 1) & 1);
+    const int xrel = r16 & 1;
+    const int zc = min(zq, p.Z - 1), yc = min(yq, p.Y - 1);
+    int ylg, yng;
+    clamp_range(min(y0g, p.Y - 1), 2, p.Y, KY, ylg, yng);
+    const int dy = ylg - ylo;
+    const int wz = win_start(zc, p.Z, KZ, false) - zlo;
+    const int wy = win_start(yc, p.Y, KY, false) - ylg;
+    const int zb = zlo - zc + KZ - 1;
+    const int yb = ylg - yc + KY - 1;
+    bool oky[2][2];
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            oky[hf][j] = (unsigned)(4 * hf + j + 2 * (g >> 1) - wy) < (unsigned)KY;
+    const int tb_lane = (zb * BY + yb + 2 * (g >> 1)) * XT + 4 * (g & 1) - xrel + 1;
+    // K operand (key 16 j + r16 = lat row 4hf + j + 2 (r16 >> 3), lon column
+    // r16 & 7 of the group halo; channels 8g .. 8g+7): LDS offsets in a slot
+    int kaddr[2][2][2];
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int G = 0; G < 2; ++G) {
+                const int R = dy + 4 * hf + j + 2 * (r16 >> 3), cc = GX * (gxa + G) + (r16 & 7);
+                kaddr[hf][j][G] = R * RING8_ROWB + cc * 32 + 8 * (g ^ (((R >> 1) & 1) << 1));
+            }
+    // V^T operand (channel r16 + 16 tt; keys 4g .. 4g+3 of lat rows R0 and
+    // R0 + 1): block (wave >> 1) + (g & 1) of row R0 = dy + 4hf + 2 (g >> 1)
+    const int vbase = RING_ROWS * RING8_ROWB + (dy + 2 * (g >> 1)) * RING8_ROWB + ((wave >> 1) + (g & 1)) * 128 + r16 * 4;
+
+    long qf[2];
+    long qtok[2];
+    bool act[2];
+    float mref[2];
+    const float mulq = q_mul(aq);
+#pragma unroll
+    for (int G = 0; G < 2; ++G) {
+        const int xp_ = x0 + GX * (gxa + G) + xrel;
+        act[G] = zq < p.Z && yq < p.Y && xp_ < p.X - SX;
+        const int xc = xp_ < 0 ? xp_ + p.X : (xp_ >= p.X ? xp_ - p.X : xp_);
+        qtok[G] = (long)mul24(mul24((unsigned)zc, (unsigned)p.Y) + (unsigned)yc, (unsigned)p.X) + xc;
+        const uint2 q8 = bf16x8_to_e4m3(*(const uint4 *)(qb + qtok[G] * p.ts + 8 * g), mulq);
+        qf[G] = (long)(((unsigned long long)q8.y << 32) | q8.x);
+        const uint2 ks = *(const uint2 *)(k8 + qtok[G] * p.ts + 8 * g);
+        mref[G] = xsum16_32(e4m3_dot4(q8.y, ks.y, e4m3_dot4(q8.x, ks.x, 0.f)));                     // the query's own score, raw units (bias below)
+    }
+    __syncthreads();     // bias table and level 0 in LDS
+    {
+        const float tcenter = tbl[((KZ - 1) * BY + KY - 1) * XT + 1 + RX];
+#pragma unroll
+        for (int G = 0; G < 2; ++G) mref[G] += tcenter;
+    }
+    const float tau_raw = TAU / c;
+    const long ones = 0x3838383838383838L;   // e4m3 1.0 in every byte
+
+    f32x4 oacc[2][2], lacc[2];
+    for (int pass = 0;; ++pass) {
+        float mx[2] = {-INFINITY, -INFINITY}, nmc[2];
+#pragma unroll
+        for (int G = 0; G < 2; ++G) {
+            oacc[G][0] = oacc[G][1] = lacc[G] = f32x4{0.f, 0.f, 0.f, 0.f};
+            nmc[G] = -c * mref[G];
+        }
+        for (int hz0 = 0; hz0 < zn; hz0 += 2)
+#pragma unroll
+        for (int lv = 0; lv < 2; ++lv) {
+            const int hz = hz0 + lv;
+            if (hz >= zn) break;                  // uniform
+            if (hz > 0) __syncthreads();          // level hz landed; level hz - 1 is done with
+            if (hz + 1 < zn) stage(hz + 1, lv ^ 1);
+            const unsigned char *sl = ring + lv * RING8_SLOT;
+            const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
+            const int tbh = tb_lane + hz * BY * XT;
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf) {
+                f32x4 binit[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int a = (okz && oky[hf][j]) ? tbh : TBL;
+                    const float *tp = tbl + a + (4 * hf + j) * XT;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) binit[j][i] = tp[i];
+                }
+                long pf[2];
+#pragma unroll
+                for (int G = 0; G < 2; ++G) {
+                    float pv[8];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const long kf = *(const long *)(sl + kaddr[hf][j][G]);
+                        const f32x4 sc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(kf, qf[G], binit[j], 0, 0, 0);
+                        mx[G] = max3f(mx[G], max3f(sc[0], sc[1], sc[2]), sc[3]);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) pv[4 * j + i] = __builtin_amdgcn_exp2f(fmaf(sc[i], c, nmc[G]));
+                    }
+                    unsigned lo = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(pv[0], pv[1], 0, false);
+                    lo = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(pv[2], pv[3], (int)lo, true);
+                    unsigned hi = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(pv[4], pv[5], 0, false);
+                    hi = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(pv[6], pv[7], (int)hi, true);
+                    pf[G] = (long)(((unsigned long long)hi << 32) | lo);
+                }
+                const unsigned char *vr = sl + vbase + 4 * hf * RING8_ROWB;
+#pragma unroll
+                for (int tt = 0; tt < 2; ++tt) {
+                    const unsigned char *vt = vr + 64 * tt;
+                    const unsigned a0 = *(const unsigned *)vt, a1 = *(const unsigned *)(vt + 128);
+                    const unsigned b0 = *(const unsigned *)(vt + RING8_ROWB), b1 = *(const unsigned *)(vt + RING8_ROWB + 128);
+                    // group 0: lon columns 0..3 of the block; group 1: columns 2, 3 and 0, 1 of the next
+                    const long v0 = (long)(((unsigned long long)b0 << 32) | a0);
+                    const long v1 = (long)(((unsigned long long)__builtin_amdgcn_alignbyte(b1, b0, 2) << 32) |
+                                           __builtin_amdgcn_alignbyte(a1, a0, 2));
+                    oacc[0][tt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(v0, pf[0], oacc[0][tt], 0, 0, 0);
+                    oacc[1][tt] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(v1, pf[1], oacc[1][tt], 0, 0, 0);
+                }
+#pragma unroll
+                for (int G = 0; G < 2; ++G)
+                    lacc[G] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(ones, pf[G], lacc[G], 0, 0, 0);
+            }
+        }
+        // weights above 2^TAU (or a non-finite result) need the exact maxima
+        int bad = 0;
+#pragma unroll
+        for (int G = 0; G < 2; ++G) {
+            bad |= !(mx[G] - mref[G] <= tau_raw);
+#pragma unroll
+            for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) bad |= !__builtin_isfinite(oacc[G][tt][i]);
+        }
+        if (!__syncthreads_or(bad) || pass == 1) break;
+        {
+            const unsigned usrow = (unsigned)p.X * tsb;
+            const unsigned urow0 = (unsigned)zlo * ((unsigned)p.Y * usrow) + (unsigned)ylo * usrow;
+            const int kslab = p.Y * p.X * (int)tsb;
+            float me[2] = {-INFINITY, -INFINITY};
+            for (int hz = 0; hz < zn; ++hz) {
+                const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
+                const int tbh = tb_lane + hz * BY * XT;
+#pragma unroll
+                for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int a = (okz && oky[hf][j]) ? tbh : TBL;
+                        const float *tp = tbl + a + (4 * hf + j) * XT;
+                        f32x4 bi;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) bi[i] = tp[i];
+                        const int hyk = min(4 * hf + j + 2 * (r16 >> 3) + dy, yn - 1);
+#pragma unroll
+                        for (int G = 0; G < 2; ++G) {
+                            int xk = hx0 + (r16 & 7) + GX * (gxa + G);
+                            xk = xk < 0 ? xk + p.X : (xk >= p.X ? xk - p.X : xk);
+                            const unsigned ko = urow0 + (unsigned)hyk * usrow + (unsigned)xk * tsb + 8u * g;
+                            const long kf = (long)__builtin_bit_cast(unsigned long long,
+                                                                   __builtin_amdgcn_raw_buffer_load_b64(krs, ko, hz * kslab, 0));
+                            const f32x4 sc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(kf, qf[G], bi, 0, 0, 0);
+                            me[G] = max3f(me[G], max3f(sc[0], sc[1], sc[2]), sc[3]);
+                        }
+                    }
+            }
+#pragma unroll
+            for (int G = 0; G < 2; ++G) mref[G] = xmax16_32(me[G]);
+        }
+        stage(0, 0);
+        __syncthreads();
+    }
+
+    const float sv = dq_scale(av);
+#pragma unroll
+    for (int G = 0; G < 2; ++G) {
+        if (!act[G]) continue;
+        const float inv = sv / lacc[G][0];
+        bf16 *ob = (bf16 *)p.out + (size_t)b * p.obs + (size_t)qtok[G] * p.ots + h * 32;
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            f32x4 v = oacc[G][tt];
+            uint2 u;
+            u.x = pack_bf16x2(v[0] * inv, v[1] * inv);
+            u.y = pack_bf16x2(v[2] * inv, v[3] * inv);
+            *(uint2 *)(ob + 16 * tt + 4 * g) = u;
+        }
+    }
+}
+
+// K (bf16, token-major with strides bs, ts, hs) -> e4m3 at the state's
+// scale amax_k / 448, same strides in bytes; 8 channels per thread.
+__global__ void k8_kernel(const bf16 *__restrict__ k, long bs, long ts, long hs, unsigned char *__restrict__ out,
+                          int B, long T, int H, const float *__restrict__ amax, int amax_stride) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long total = (long)B * T * H * 4;
+    if (e >= total) return;
+    const int c = (int)(e & 3);
+    long r = e >> 2;
+    const int h = (int)(r % H); r /= H;
+    const long t = r % T;
+    const int b = (int)(r / T);
+    const size_t off = (size_t)b * bs + (size_t)t * ts + (size_t)h * hs + 8 * c;
+    *(uint2 *)(out + off) = bf16x8_to_e4m3(*(const uint4 *)(k + off), q_mul(amax[(size_t)b * amax_stride + 1]));
+}
+
+// V (bf16, token-major) -> e4m3 at the state's scale amax_v / 448 in the
+// blocked layout with byte elements: one thread per (head, state, level,
+// lat, block of 4 positions, 8 channels).
+__global__ void v8_blocked_kernel(const bf16 *__restrict__ v, long bs, long ts, long hs, unsigned char *__restrict__ out,
+                                  int B, int Z, int Y, int X, int H, int xp, const float *__restrict__ amax,
+                                  int amax_stride) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nxb = xp >> 2;
+    const long total = (long)H * B * Z * Y * nxb * 4;
+    if (e >= total) return;
+    const int c = (int)(e & 3);
+    long r = e >> 2;
+    const int xb = (int)(r % nxb); r /= nxb;
+    const long zyb = r;
+    const int y = (int)(r % Y); r /= Y;
+    const int z = (int)(r % Z); r /= Z;
+    const int b = (int)(r % B);
+    const int h = (int)(r / B);
+    const float mul = q_mul(amax[(size_t)b * amax_stride + 2]);
+    uint2 q8[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int x = 4 * xb + k - 4;
+        x = ((x % X) + X) % X;
+        q8[k] = bf16x8_to_e4m3(*(const uint4 *)(v + (size_t)b * bs + (((size_t)z * Y + y) * X + x) * ts + (size_t)h * hs + 8 * c), mul);
+    }
+    // channel 8c + i of the 4 positions -> one dword (byte k = position k)
+    unsigned *dst = (unsigned *)(out + ((size_t)zyb * nxb + xb) * 128 + (8 * c) * 4);
+    const unsigned lo01 = __builtin_amdgcn_perm(q8[1].x, q8[0].x, 0x05010400u);   // p0c0 p1c0 p0c1 p1c1
+    const unsigned lo23 = __builtin_amdgcn_perm(q8[3].x, q8[2].x, 0x05010400u);
+    const unsigned hi01 = __builtin_amdgcn_perm(q8[1].x, q8[0].x, 0x07030602u);   // c2, c3
+    const unsigned hi23 = __builtin_amdgcn_perm(q8[3].x, q8[2].x, 0x07030602u);
+    const unsigned lo01b = __builtin_amdgcn_perm(q8[1].y, q8[0].y, 0x05010400u);
+    const unsigned lo23b = __builtin_amdgcn_perm(q8[3].y, q8[2].y, 0x05010400u);
+    const unsigned hi01b = __builtin_amdgcn_perm(q8[1].y, q8[0].y, 0x07030602u);
+    const unsigned hi23b = __builtin_amdgcn_perm(q8[3].y, q8[2].y, 0x07030602u);
+    dst[0] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+    dst[1] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+    dst[2] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+    dst[3] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+    dst[4] = __builtin_amdgcn_perm(lo23b, lo01b, 0x05040100u);
+    dst[5] = __builtin_amdgcn_perm(lo23b, lo01b, 0x07060302u);
+    dst[6] = __builtin_amdgcn_perm(hi23b, hi01b, 0x05040100u);
+    dst[7] = __builtin_amdgcn_perm(hi23b, hi01b, 0x07060302u);
+}
+
 template <int KZ, int KY, int KX>
 __global__ __launch_bounds__(256, 2) void nat_tile_fp8_kernel(NatArgs p, int ZWmax, int YR, TileDiv dm) {
     constexpr int RX = (KX - 1) / 2;
@@ -1201,8 +1571,30 @@ hipError_t launch_tile_fp8(const NatArgs &a, hipStream_t stream) {
     return hipGetLastError();
 }
 
+size_t ring8_lds(int Kz, int Ky) {
+    const int tblp = (((2 * Kz - 1) * (2 * Ky - 1) * XT + NEG_RUN + 3) & ~3);
+    return (size_t)tblp * 4 + 2 * (size_t)RING8_SLOT;
+}
+
+template <int KZ, int KY, int KX>
+hipError_t launch_ring_fp8(const NatArgs &a, hipStream_t stream) {
+    // exactly the dynamic size: the kernel also holds a little static LDS (__syncthreads_or)
+    static const hipError_t attr_err = hipFuncSetAttribute((const void *)nat_ring_fp8_kernel<KZ, KY, KX>,
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                           (int)ring8_lds(KZ, KY));
+    if (attr_err != hipSuccess) return attr_err;
+    constexpr int TBLP = tbl_padded<KZ, KY, KX>();
+    nat_bias_prep_fp8<KZ, KY, KX><<<(a.B * a.H * TBLP + 255) / 256, 256, 0, stream>>>(a);
+    const int ntiles = ((a.Z + TZ - 1) / TZ) * ((a.Y + TY - 1) / TY) * ((a.X + TX - 1) / TX);
+    const long total = (long)ntiles * a.H * a.B;
+    const unsigned grid = (unsigned)(((total + 7) >> 3) << 3);
+    nat_ring_fp8_kernel<KZ, KY, KX><<<grid, 256, ring8_lds(KZ, KY), stream>>>(a, tile_div(a));
+    return hipGetLastError();
+}
+
 template <int KZ, int KY, int KX>
 hipError_t launch_tile(const NatArgs &a, hipStream_t stream) {
+    if (a.amax && a.vt) return launch_ring_fp8<KZ, KY, KX>(a, stream);
     if (a.amax) return launch_tile_fp8<KZ, KY, KX>(a, stream);
     if (a.vt) {
         if (a.qscale == 1.0f) return launch_ring<KZ, KY, KX, true>(a, stream);
@@ -1232,12 +1624,13 @@ size_t nat_tile_lds_bytes(const NatArgs &a) {
             if (total * d >= (1L << 32)) return 0;
     }
     if (a.vt) {
-        // blocked V: every halo row must be one in-range 1 KB run, and a
-        // (head, state) plane must be addressable with 32-bit offsets
-        if (a.amax || a.xp < v_blocked_xp(a.X)) return 0;
+        // blocked V: every halo row must be one in-range run, and a (head,
+        // state) plane must be addressable with 32-bit offsets
+        if (a.xp < v_blocked_xp(a.X)) return 0;
         if ((long)a.Z * a.Y * a.xp * 64 >= (1L << 31)) return 0;
+        if (a.amax && a.B > 64) return 0;
+        return a.amax ? ring8_lds(a.Kz, a.Ky) : ring_lds(a.Kz, a.Ky);
     }
-    if (a.vt) return ring_lds(a.Kz, a.Ky);
     const int zw = max_halo(a.Z, a.Kz, TZ), yr = std::max(max_halo(a.Y, a.Ky, TY), YR_MIN);
     return a.amax ? tile_lds_fp8(a.Kz, a.Ky, zw, yr) : tile_lds(a.Kz, a.Ky, zw, yr);
 }
@@ -1255,6 +1648,19 @@ hipError_t launch_nat_bias_table(const NatArgs &a, hipStream_t stream) {
     if (a.Kz == 3 && a.Ky == 5 && a.Kx == 5) return bias_table_only<3, 5, 5>(a, stream);
     if (a.Kz == 3 && a.Ky == 3 && a.Kx == 3) return bias_table_only<3, 3, 3>(a, stream);
     return hipErrorNotSupported;
+}
+
+hipError_t launch_kv8(const NatArgs &a, unsigned char *k8, unsigned char *v8, hipStream_t stream) {
+    if (!a.amax || (a.xp & 3)) return hipErrorInvalidValue;
+    const long T = (long)a.Z * a.Y * a.X;
+    const long nk = (long)a.B * T * a.H * 4, nv = (long)a.H * a.B * a.Z * a.Y * (a.xp / 4) * 4;
+    if (nk > 0x7fffffffL || nv > 0x7fffffffL) return hipErrorInvalidValue;
+    if (nk) k8_kernel<<<(unsigned)((nk + 255) / 256), 256, 0, stream>>>((const bf16 *)a.k, a.bs, a.ts, a.hs, k8, a.B, T,
+                                                                      a.H, a.amax, a.amax_stride);
+    if (nv) v8_blocked_kernel<<<(unsigned)((nv + 255) / 256), 256, 0, stream>>>((const bf16 *)a.v, a.bs, a.ts, a.hs, v8,
+                                                                              a.B, a.Z, a.Y, a.X, a.H, a.xp, a.amax,
+                                                                              a.amax_stride);
+    return hipGetLastError();
 }
 
 hipError_t launch_v_blocked(const NatArgs &a, void *out, hipStream_t stream) {

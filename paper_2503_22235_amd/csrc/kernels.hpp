@@ -164,8 +164,9 @@ struct NatArgs {
     // run on e4m3 codes with the scales amax/448.
     const float *amax;
     int amax_stride;
-    // bf16 only: v is in the blocked layout of v_blocked_offset (vt = 1)
-    // with xp padded lon positions per row; q is pre-scaled (qscale = 1)
+    // v is in the blocked layout of v_blocked_offset (vt = 1) with xp padded
+    // lon positions per row: bf16 elements with q pre-scaled (qscale = 1),
+    // or (amax set) e4m3 bytes from launch_kv8 with k in e4m3 as well
     int vt;
     int xp;
 };
@@ -197,6 +198,10 @@ hipError_t launch_nat_tile(const NatArgs &a, hipStream_t stream);
 // Copies a.v (bf16, token-major with strides bs, ts, hs) into `out` in the
 // blocked layout of v_blocked_offset with a.xp positions per row.
 hipError_t launch_v_blocked(const NatArgs &a, void *out, hipStream_t stream);
+// FP8: a.k and a.v (bf16, token-major) quantized with each state's scales
+// (a.amax, folded) into e4m3: k8 with the same strides (in bytes), v8 in the
+// blocked layout with byte elements and a.xp positions per row.
+hipError_t launch_kv8(const NatArgs &a, unsigned char *k8, unsigned char *v8, hipStream_t stream);
 
 // --- index tables (same window functions as the attention kernels) ------
 hipError_t launch_nat_indices(int Z, int Y, int X, int Kz, int Ky, int Kx,

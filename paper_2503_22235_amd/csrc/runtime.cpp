@@ -9,12 +9,21 @@ namespace wm {
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// FP8 block: the region of the e4m3 MLP hidden state, which also holds the
+// e4m3 k and blocked v of the attention before it (M C + B Z Y xp C bytes).
+static size_t fp8_h8_bytes(const wm_processor *p, int B) {
+    const size_t M = (size_t)B * p->g.Z * p->g.Y * p->g.X;
+    const size_t C = p->g.C, F = C * p->mlp;
+    const size_t kv = al256(M * C) + (size_t)B * p->g.Z * p->g.Y * v_blocked_xp(p->g.X) * C;
+    return al256(std::max(M * F, kv));
+}
+
 size_t block_workspace_bytes(const wm_processor *p, int B) {
     const size_t M = (size_t)B * p->g.Z * p->g.Y * p->g.X;
     const size_t C = p->g.C, F = C * p->mlp;
     if (p->prec == WM_FP8_E4M3) {
-        // u8/w8 | qkv or h (bf16) | o (bf16) | h8 | bias tables | amax slots
-        return al256(M * C) + al256(M * std::max(3 * C, F) * 2) + al256(M * C * 2) + al256(M * F) +
+        // u8/w8 | qkv or h (bf16) | o (bf16) | h8, or k8 and blocked v8 | bias tables | amax slots
+        return al256(M * C) + al256(M * std::max(3 * C, F) * 2) + al256(M * C * 2) + fp8_h8_bytes(p, B) +
                (size_t)B * p->g.heads * NAT_TBL_WS_FLOATS * 4 + (size_t)AMAX_SHARDS * AMAX_STRIDE * 4;
     }
     const size_t esz = p->prec == WM_BF16 ? 2 : 4;
@@ -201,7 +210,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     char *big = base + al256((size_t)M * C);
     char *obuf = big + al256((size_t)M * std::max(3 * C, F) * 2);
     unsigned char *h8 = (unsigned char *)(obuf + al256((size_t)M * C * 2));
-    float *tbl_ws = (float *)((char *)h8 + al256((size_t)M * F));
+    float *tbl_ws = (float *)((char *)h8 + fp8_h8_bytes(p, B));
     unsigned *amax = (unsigned *)((char *)tbl_ws + (size_t)B * H * NAT_TBL_WS_FLOATS * 4);
     unsigned *amax_qkv = amax + B, *amax_h = amax + 5 * B;
     hipError_t e;
@@ -252,7 +261,22 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     na.tbl_ws = tbl_ws;
     na.amax = (const float *)amax_qkv;
     na.amax_stride = 3;
-    WM_TIMED(PK_NA, launch_nat(na, true, s), "NA")
+    // the e4m3 ring kernel: k and v quantized once into the h8 region (free
+    // until MLP1), v in the blocked layout; timed with the attention
+    auto attention = [&]() -> hipError_t {
+        NatArgs nr = na;
+        nr.vt = 1;
+        nr.xp = v_blocked_xp(g.X);
+        const size_t lds = nat_tile_lds_bytes(nr);
+        if (lds == 0 || lds > 160 * 1024) return launch_nat(na, true, s);
+        unsigned char *k8 = h8, *v8 = h8 + al256((size_t)M * C);
+        hipError_t err = launch_kv8(nr, k8, v8, s);
+        if (err != hipSuccess) return err;
+        nr.k = k8;
+        nr.v = v8;
+        return launch_nat(nr, true, s);
+    };
+    WM_TIMED(PK_NA, attention(), "NA")
     EpiArgs er{};
     er.bias = w.b_o;
     er.resid = x;
