@@ -11,8 +11,8 @@
 // bf16 or 128 e4m3 values for 128-byte rows).  Each stage is written
 // straight from global memory into LDS by buffer_load_dwordx4 ... lds (no
 // register staging): the activation tile and the weight tile through rings
-// of two slots each, one stage ahead (a three-slot activation ring, two
-// stages ahead, is a launch option).  A workgroup
+// of D slots each, D - 1 stages ahead (D = 2 on the shapes launched here).
+// A workgroup
 // owns one token tile and walks one or more
 // output-feature tiles; the stage stream runs on across tile boundaries, so
 // the next tile's first loads are in flight while the previous tile's
@@ -154,6 +154,19 @@ __device__ __forceinline__ void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// Wait until at most min(later, D - 2) stages of PER load instructions each
+// are still in flight (later: stages issued after the one waited for).
+template <int PER, int D>
+__device__ __forceinline__ void wait_stages(int later) {
+    if constexpr (D >= 5)
+        if (later >= 3) return wait_vmcnt<3 * PER>();
+    if constexpr (D >= 4)
+        if (later >= 2) return wait_vmcnt<2 * PER>();
+    if constexpr (D >= 3)
+        if (later >= 1) return wait_vmcnt<PER>();
+    wait_vmcnt<0>();
+}
+
 // The MFMAs of one K stage for a wave's TM x TN tiles.  FIRST: the stage is
 // the tile's first, so its first k-step adds to zero instead of acc.
 // SWAP (bf16): the activation tile is the MFMA "A" operand, so a lane holds
@@ -267,10 +280,9 @@ __device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, const float *bias
 // FP8: operands are e4m3 bytes (128 k-values per 128-byte stage, MFMA
 // 16x16x128 f8f6f4, one k-step per stage); the epilogue dequantizes per row.
 // WGM x WGN waves tile the BM x BN output; OCC workgroups share a CU.
-// The activation tile of each K stage streams through a ring of SA slots
-// (SA - 1 stages ahead: it comes from HBM) and the weight tile through a
-// ring of SW slots (SW - 1 ahead: it stays in L2); SW = 2, SA = 2 or 3.
-template <int BM, int BN, int BKB, int SA, int SW, int WGM, int WGN, int OCC, int EPI, bool FP8>
+// The activation and weight tiles of each K stage stream through two rings
+// of D slots each, D - 1 stages ahead of the MFMAs.
+template <int BM, int BN, int BKB, int D, int WGM, int WGN, int OCC, int EPI, bool FP8>
 __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const void *__restrict__ A, const void *__restrict__ W,
                                                          int M, int N, int K, EpiArgs ep, int tpw, int rw) {
 #if defined(__HIP_DEVICE_COMPILE__)   // LDS-address-space builtins exist only in the device pass
@@ -285,9 +297,9 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
     static_assert(BKB == 128 || BKB == 64, "stage row bytes");
     static_assert(BM % (RPI * NW) == 0 && BN % (RPI * NW) == 0, "rows per stage must split over the waves");
     static_assert(WM % 16 == 0 && WN % 16 == 0, "wave tile");
-    static_assert(SW == 2 && (SA == 2 || SA == 3), "ring depths");
+    static_assert(D >= 2 && D <= 5, "ring depth");
     extern __shared__ __align__(16) unsigned char smem[];
-    unsigned char *const aring = smem, *const wring = smem + SA * ABYTES;
+    unsigned char *const aring = smem, *const wring = smem + D * ABYTES;
 
     // A workgroup computes nn tiles: feature tiles tn0 .. tn0+nn-1 of row
     // block m0 (rw == 0), or row blocks m0, m0+BM, .. of feature tile tn0
@@ -331,7 +343,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
     // stage s of the stream = k-stage (s % nk) of tile (s / nk)
     auto issue_a = [&](int s) {
         const int t = s / nk, kt = s - t * nk;
-        unsigned char *sbase = aring + (s % SA) * ABYTES;
+        unsigned char *sbase = aring + (s % D) * ABYTES;
         // the row advance goes into the vector offset: rows past M must fail
         // the buffer range check and read zero
         const unsigned aadv = (unsigned)t * astep;
@@ -342,7 +354,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
     };
     auto issue_w = [&](int s) {
         const int t = s / nk, kt = s - t * nk;
-        unsigned char *sbase = wring + (s % SW) * WBYTES;
+        unsigned char *sbase = wring + (s % D) * WBYTES;
         const unsigned wsoff = (unsigned)t * wstep + kt * BKB;
 #pragma unroll
         for (int i = 0; i < LPB; ++i)
@@ -369,13 +381,16 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         woff[o] = (wn * WN + r16) * BKB + pc;
     }
 
-    // Issue order: A(0), W(0), A(1) (SA = 3), then in iteration st W(st+1)
-    // and A(st+SA-1).  So when iteration st waits, only A(st+1) (SA = 3) was
-    // issued after W(st), and A(st) before it.
+    // Issue order: A(0), W(0), .., A(D-2), W(D-2), then in iteration st
+    // A(st+D-1), W(st+D-1).  So when iteration st waits, the loads of stages
+    // st+1 .. st+D-2 (those that exist) may stay in flight.
     const int S = nn * nk;
-    issue_a(0);
-    issue_w(0);
-    if (SA == 3 && S > 1) issue_a(1);
+#pragma unroll
+    for (int s0 = 0; s0 < D - 1; ++s0)
+        if (s0 < S) {
+            issue_a(s0);
+            issue_w(s0);
+        }
 
     // The tiles of this workgroup.  SWAP (the V tiles of a bf16 QKV
     // projection with ep.vt set; a workgroup's tiles are all V or none):
@@ -392,16 +407,17 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         for (int kt = 0; kt < nk; ++kt) {
             const int st = t * nk + kt;
             // This wave's loads of stage st have landed once at most the
-            // loads of A(st+1) are outstanding; the barrier then makes all
-            // waves' parts of stage st visible and frees the slots read in
-            // iteration st - 1.  (A bare s_barrier: __syncthreads() would
+            // loads of the later stages already issued are outstanding (loads
+            // return in order); the barrier then makes all waves' parts of
+            // stage st visible and frees the slots read in iteration st - 1.  (A bare s_barrier: __syncthreads() would
             // also drain the loads still in flight.)
-            if (SA == 3 && st + 1 < S) wait_vmcnt<LPA>();
-            else wait_vmcnt<0>();
+            wait_stages<LPA + LPB, D>(S - 1 - st);
             __builtin_amdgcn_s_barrier();
-            if (st + 1 < S) issue_w(st + 1);
-            if (st + SA - 1 < S) issue_a(st + SA - 1);
-            const unsigned char *sbA = aring + (st % SA) * ABYTES, *sbW = wring + (st % SW) * WBYTES;
+            if (st + D - 1 < S) {
+                issue_a(st + D - 1);
+                issue_w(st + D - 1);
+            }
+            const unsigned char *sbA = aring + (st % D) * ABYTES, *sbW = wring + (st % D) * WBYTES;
             // ZSTART: a tile's first k-step starts its accumulators from an
             // inline zero operand instead of registers cleared in the previous
             // epilogue (not for the FP8 and rotary variants, whose extra
@@ -557,20 +573,20 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
 // (measured); other N of 1536 or more take 2, smaller N take 1.
 inline int wide_tpw(int N) { return N == 1536 ? 3 : (N == 2048 ? 4 : (N >= 1536 ? 2 : 1)); }
 
-template <int BM, int BN, int BKB, int SA, int SW, int WGM, int WGN, int OCC, bool FP8>
+template <int BM, int BN, int BKB, int D, int WGM, int WGN, int OCC, bool FP8>
 hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                       hipStream_t stream, int tpw_default = 1, int rw_default = 0) {
-    constexpr size_t lds = (size_t)SA * BM * BKB + (size_t)SW * BN * BKB;
+    constexpr size_t lds = (size_t)D * (BM + BN) * BKB;
     static_assert(lds * OCC <= 160 * 1024, "LDS per CU");
     constexpr int NTH = 64 * WGM * WGN;
     // LDS limit of the variants, set once per process (a local static's
     // initialisation is thread-safe; the server thread launches too)
     static const hipError_t attr_err = [] {
-        const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_QKV, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_GELU, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_RESID, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_STORE, FP8>};
+        const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_QKV, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_GELU, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_RESID, FP8>,
+                              (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_STORE, FP8>};
         for (const void *f : fns) {
             const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
@@ -608,19 +624,19 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
         const int grid = ((total + 7) >> 3) << 3;
         switch (epi) {
         case EPI_QKV:
-            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_QKV, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_QKV, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         case EPI_QKV_ROPE:
-            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_QKV_ROPE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_QKV_ROPE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         case EPI_GELU:
-            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_GELU, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_GELU, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         case EPI_RESID:
-            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_RESID, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_RESID, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         default:
-            gemm_lds_kernel<BM, BN, BKB, SA, SW, WGM, WGN, OCC, EPI_STORE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+            gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_STORE, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
         }
         const hipError_t err = hipGetLastError();
@@ -629,20 +645,15 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
     return hipSuccess;
 }
 
-// Depth of the activation ring: 2 (one stage ahead), or 3 with
-// WM_GEMM_SA=3 (two ahead; measured no faster on the block's shapes, whose
-// main loop is bound by LDS traffic -- fragment reads plus the stage writes --
-// rather than by load latency).
-template <int BM, int BN, int BKB, int WGM, int WGN, int OCC, bool FP8>
+// 128-byte stages in rings of 2, one stage ahead.  Measured on the block's
+// shapes (8x90x180, C = 512): 64-byte stages in rings of 4 or 5 (three or
+// four stages ahead) are 8-10% slower, and so are two 4-wave workgroups per
+// CU on 128 x 256 or 256 x 128 tiles: the per-stage barrier costs more than
+// the load latency that deeper rings hide.
+template <int BM, int BN, int WGM, int WGN, int OCC, bool FP8>
 hipError_t launch_sa(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                      hipStream_t stream, int tpw_default = 1, int rw_default = 0) {
-    static const int sa = [] {
-        const char *v = getenv("WM_GEMM_SA");
-        return v && atoi(v) == 3 ? 3 : 2;
-    }();
-    if (sa == 3)
-        return launch_cfg<BM, BN, BKB, 3, 2, WGM, WGN, OCC, FP8>(A, W, M, N, K, epi, ep, stream, tpw_default, rw_default);
-    return launch_cfg<BM, BN, BKB, 2, 2, WGM, WGN, OCC, FP8>(A, W, M, N, K, epi, ep, stream, tpw_default, rw_default);
+    return launch_cfg<BM, BN, 128, 2, WGM, WGN, OCC, FP8>(A, W, M, N, K, epi, ep, stream, tpw_default, rw_default);
 }
 
 }  // namespace glds
@@ -670,27 +681,28 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
     // (a QKV feature tile must not straddle two of Q, K and V: BN divides C)
     const bool n256 = N % 256 == 0 && (!epi_qkv(epi) || ep.C % 256 == 0);
     switch (cfg) {
-    case 0: return launch_sa<128, 128, 128, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
-    case 3: return launch_cfg<256, 128, 128, 2, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
-    case 4: return launch_cfg<256, 128, 128, 3, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
-    case 9: return launch_cfg<256, 128, 64, 3, 2, 4, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
+    case 0: return launch_sa<128, 128, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
+    case 3: return launch_cfg<256, 128, 128, 2, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream);
     default: break;
     }
+    auto wide = [&](int tpw, int rw) -> hipError_t {
+        return launch_sa<256, 256, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, tpw, rw);
+    };
     if (epi_qkv(epi) && ep.vt) {
         // a workgroup's feature tiles must be all V or none: walk 2 when a
         // part (C columns) holds an even number of tiles, else 1
         const int bn = n256 ? 256 : 128, per_part = ep.C / bn;
-        if (n256) return launch_sa<256, 256, 128, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
-        return launch_sa<128, 128, 128, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
+        if (n256) return wide(per_part % 2 ? 1 : 2, 0);
+        return launch_sa<128, 128, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
     }
     if (n256) {
         // N = 512 (the out-projection and MLP2 at C = 512): two row blocks of
         // one feature tile per workgroup (measured 2-3% faster than one tile
         // per workgroup; walking feature tiles is faster for wide N)
-        if (N == 512) return launch_sa<256, 256, 128, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, 2, 1);
-        return launch_sa<256, 256, 128, 4, 2, 1, false>(A, W, M, N, K, epi, ep, stream, wide_tpw(N), 0);
+        if (N == 512) return wide(2, 1);
+        return wide(wide_tpw(N), 0);
     }
-    return launch_sa<128, 128, 128, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
+    return launch_sa<128, 128, 2, 2, 2, false>(A, W, M, N, K, epi, ep, stream);
 }
 
 hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
@@ -703,10 +715,10 @@ hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, Ep
     }();
     if (N % 256 == 0 && (!epi_qkv(epi) || ep.C % 256 == 0) && cfg != 0) {
         // N = 512 (MLP2 at C = 512): row walk, as in launch_gemm_lds
-        if (N == 512) return launch_sa<256, 256, 128, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, 2, 1);
-        return launch_sa<256, 256, 128, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, wide_tpw(N), 0);
+        if (N == 512) return launch_sa<256, 256, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, 2, 1);
+        return launch_sa<256, 256, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, wide_tpw(N), 0);
     }
-    return launch_sa<128, 128, 128, 2, 2, 2, true>(A, W, M, N, K, epi, ep, stream);
+    return launch_sa<128, 128, 2, 2, 2, true>(A, W, M, N, K, epi, ep, stream);
 }
 
 }  // namespace wm
