@@ -68,6 +68,21 @@ bool fp8_attention_applies(const wm_grid *g, int B, long ts) {
     return lds > 0 && lds <= 160 * 1024;
 }
 
+bool fp8_ring_applies(const wm_grid *g, int B) {
+    static float dummy_tbl;
+    static float dummy_amax;
+    NatArgs a{};
+    a.ts = 32;
+    a.B = B; a.Z = g->Z; a.Y = g->Y; a.X = g->X; a.H = g->heads;
+    a.Kz = g->Kz; a.Ky = g->Ky; a.Kx = g->Kx; a.periodic = g->periodic_mask;
+    a.tbl_ws = &dummy_tbl;       // only tested for null
+    a.amax = &dummy_amax;
+    a.vt = 1;
+    a.xp = v_blocked_xp(g->X);
+    const size_t lds = nat_tile_lds_bytes(a);
+    return lds > 0 && lds <= 160 * 1024;
+}
+
 // Whether the bf16 attention on v in the blocked layout (the level-ring
 // kernel) covers grid g at batch B with q/k token stride ts (elements).
 bool ring_attention_applies(const wm_grid *g, int B, long ts) {
@@ -340,7 +355,7 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
     if (prec != WM_F32 && prec != WM_BF16 && prec != WM_FP8_E4M3)
         return fail(WM_EINVAL, "processor precision %d not supported", (int)prec);
     // (head-major q, k, v: 32 elements per token)
-    if (prec == WM_FP8_E4M3 && !fp8_attention_applies(g, 1, 32))
+    if (prec == WM_FP8_E4M3 && !fp8_ring_applies(g, 1))
         return fail(WM_EINVAL, "FP8 processors run QK and PV on e4m3 codes, which needs lon-periodic only "
                                "(periodic_mask 4), a 5x7x7, 3x5x5 or 3x3x3 window and lon >= 8 + Kx - 1");
     if (!host_params) return fail(WM_EINVAL, "host_params is NULL");
@@ -357,13 +372,12 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
     p->device = ctx->device;
     const int C = g->C, F = C * mlp_ratio, H = g->heads;
     const size_t nrpb = (size_t)H * (2 * g->Kz - 1) * (2 * g->Ky - 1) * (2 * g->Kx - 1);
-    // Bytes per weight element: float32, bfloat16, or (FP8) e4m3 for the QKV
-    // and MLP matrices with the output projection kept in bfloat16.
+    // Bytes per weight element: float32, bfloat16, or (FP8) e4m3.
     const bool fp8 = prec == WM_FP8_E4M3;
     const size_t esz = prec == WM_F32 ? 4 : 2;
     const size_t esz_big = fp8 ? 1 : esz;
     // Device image per block: float32 vectors, then the four transposed weights.
-    const size_t nvec = 2 * C + 3 * C + nrpb + C + 2 * C + F + C + 2;
+    const size_t nvec = 2 * C + 3 * C + nrpb + C + 2 * C + F + C + 5;
     const size_t nw_bytes = ((size_t)3 * C * C + (size_t)F * C * 2) * esz_big + (size_t)C * C * esz + 4 * 256;
     auto align = [](size_t b) { return (b + 255) & ~(size_t)255; };
     // BF16: room for the tiled attention kernel's prepared bias table
@@ -450,20 +464,45 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
                     m = std::max(m, std::fabs((double)gm[c]) * std::sqrt((double)(C - 1)) + std::fabs((double)bt[c]));
                 return (float)m;
             };
-            const float a2[2] = {ln_bound(ln1_g, ln1_b), ln_bound(ln2_g, ln2_b)};
-            const float *d2 = nullptr;
-            put_vec(a2, 2, 1.f, &d2);
-            bw.ln1_amax = d2;
-            bw.ln2_amax = d2 + 1;
-            bw.ln1_amax_h = a2[0];
-            bw.ln2_amax_h = a2[1];
+            // bound of output j of a projection [in = C][outn] (source layout
+            // [in][out]) fed by LayerNorm (gamma, beta): sum_c |W_jc| L_c + |b_j|
+            auto proj_bound = [&](const float *wt, const float *bias, int outn, int j, const float *gm,
+                                  const float *bt) {
+                double u = std::fabs((double)bias[j]);
+                const double r = std::sqrt((double)(C - 1));
+                for (int c = 0; c < C; ++c)
+                    u += std::fabs((double)wt[(size_t)c * outn + j]) * (std::fabs((double)gm[c]) * r + std::fabs((double)bt[c]));
+                return u;
+            };
+            double part_max[3] = {0.0, 0.0, 0.0};
+            for (int j = 0; j < 3 * C; ++j)
+                part_max[j / C] = std::max(part_max[j / C], proj_bound(w_qkv, b_qkv, 3 * C, j, ln1_g, ln1_b));
+            // q and k: times sqrt 2, so the bound also holds once rotary (set
+            // after creation) mixes each channel pair
+            const double rot = std::sqrt(2.0);
+            const float aq = (float)(part_max[0] * rot * (LOG2E / std::sqrt(32.0)));
+            const float ak = (float)(part_max[1] * rot), av = (float)part_max[2];
+            double hmax = 0.17;
+            for (int j = 0; j < F; ++j) hmax = std::max(hmax, proj_bound(w_1, b_1, F, j, ln2_g, ln2_b));
+            const float a5[5] = {ln_bound(ln1_g, ln1_b), ln_bound(ln2_g, ln2_b), aq, ak, av};
+            const float *d5 = nullptr;
+            put_vec(a5, 5, 1.f, &d5);
+            bw.ln1_amax = d5;
+            bw.ln2_amax = d5 + 1;
+            bw.qkv_amax = d5 + 2;
+            bw.ln1_amax_h = a5[0];
+            bw.ln2_amax_h = a5[1];
+            bw.qkv_amax_h[0] = aq;
+            bw.qkv_amax_h[1] = ak;
+            bw.qkv_amax_h[2] = av;
+            bw.h_amax_h = (float)hmax;
         }
         // QKV and MLP1 rows permuted (their epilogues store 8 features per
         // lane); the residual GEMMs keep the natural order
         // (bf16: the V rows of W_qkv keep their order; the V tiles of the
         // projection write the blocked layout with swapped operands)
-        bw.dq_qkv = put_wt(w_qkv, C, 3 * C, &bw.w_qkv, fp8, fp8 ? 3 * C : 2 * C);
-        put_wt(w_o, C, C, &bw.w_o, false, 0);
+        bw.dq_qkv = put_wt(w_qkv, C, 3 * C, &bw.w_qkv, fp8, 2 * C);
+        bw.dq_o = put_wt(w_o, C, C, &bw.w_o, fp8, 0);
         bw.dq_1 = put_wt(w_1, C, F, &bw.w_1, fp8, F);
         bw.dq_2 = put_wt(w_2, F, C, &bw.w_2, fp8, 0);
         if ((e = hipMemcpy(dev, img.data(), blk_bytes, hipMemcpyHostToDevice)) != hipSuccess) {

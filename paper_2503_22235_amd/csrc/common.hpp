@@ -40,6 +40,16 @@ __device__ __forceinline__ float bf2f(bf16 b) {
     return bf_bits2f(__builtin_bit_cast(unsigned short, b));
 }
 
+// Four floats -> four OCP e4m3 codes (byte i = value i), round to nearest
+// even, saturated at +-448 (the gfx950 conversion instruction rounds; the
+// clamp keeps out-of-range values finite).
+__device__ __forceinline__ unsigned e4m3x4(float a, float b, float c, float d) {
+    const unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(fminf(fmaxf(a, -448.0f), 448.0f),
+                                                                  fminf(fmaxf(b, -448.0f), 448.0f), 0, false);
+    return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(fminf(fmaxf(c, -448.0f), 448.0f),
+                                                     fminf(fmaxf(d, -448.0f), 448.0f), (int)w, true);
+}
+
 // Loads/stores of element type T as float.
 template <typename T> struct Elt;
 template <> struct Elt<float> {

@@ -62,8 +62,9 @@ __device__ __forceinline__ void store4(bf16 *p, f32x4 v) {
 
 // Epilogue on four consecutive output features n..n+3 of token m.  For the
 // QKV scatter, `qkv_base` is the element offset of (part, head 0, token 0)
-// of the tile's part, `hc` the channel within the part and `qs` the Q scale
-// (1 for K and V): all but hc are uniform over the tile.
+// of the tile's part, `hc` the channel within the part and `qs` the factor
+// of the part (the Q scale or 1, times out_mul[part] when e4m3 codes are
+// stored): all but hc are uniform over the tile.
 template <int EPI>
 __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int n, f32x4 v,
                                            size_t qkv_base, int hc, float qs, float dq, float4 b, float4 rr) {
@@ -78,10 +79,17 @@ __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int
             v[0] = r[0]; v[1] = r[1]; v[2] = r[2]; v[3] = r[3];
         }
         v[0] *= qs; v[1] *= qs; v[2] *= qs; v[3] *= qs;
-        store4((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * ep.Mtot + m) * 32 + (hc & 31), v);
+        const size_t o = qkv_base + ((size_t)(hc >> 5) * ep.Mtot + m) * 32 + (hc & 31);
+        if (ep.out8) *(unsigned *)((unsigned char *)ep.out + o) = e4m3x4(v[0], v[1], v[2], v[3]);
+        else store4((bf16 *)ep.out + o, v);
     } else if constexpr (EPI == EPI_GELU) {
         v[0] = gelu_as(v[0]); v[1] = gelu_as(v[1]); v[2] = gelu_as(v[2]); v[3] = gelu_as(v[3]);
-        store4((bf16 *)ep.out + (size_t)m * N + n, v);
+        if (ep.out8) {
+            const float om = ep.out_mul[0];
+            *(unsigned *)((unsigned char *)ep.out + (size_t)m * N + n) = e4m3x4(v[0] * om, v[1] * om, v[2] * om, v[3] * om);
+        } else {
+            store4((bf16 *)ep.out + (size_t)m * N + n, v);
+        }
     } else if constexpr (EPI == EPI_RESID) {
         // rr: the residual values at (m, n..n+3), loaded by the caller
         *(float4 *)(ep.resid + (size_t)m * N + n) = make_float4(rr.x + v[0], rr.y + v[1], rr.z + v[2], rr.w + v[3]);
@@ -124,11 +132,19 @@ __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, in
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] *= qs;
-        store8((bf16 *)ep.out + qkv_base + ((size_t)(hc >> 5) * ep.Mtot + mg) * 32 + (hc & 31), v);
+        const size_t o = qkv_base + ((size_t)(hc >> 5) * ep.Mtot + mg) * 32 + (hc & 31);
+        if (ep.out8) *(uint2 *)((unsigned char *)ep.out + o) = make_uint2(e4m3x4(v[0], v[1], v[2], v[3]), e4m3x4(v[4], v[5], v[6], v[7]));
+        else store8((bf16 *)ep.out + o, v);
     } else if constexpr (EPI == EPI_GELU) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = gelu_as(v[i]);
-        store8((bf16 *)ep.out + (size_t)mg * N + n, v);
+        if (ep.out8) {
+            const float om = ep.out_mul[0];
+            *(uint2 *)((unsigned char *)ep.out + (size_t)mg * N + n) =
+                make_uint2(e4m3x4(v[0] * om, v[1] * om, v[2] * om, v[3] * om), e4m3x4(v[4] * om, v[5] * om, v[6] * om, v[7] * om));
+        } else {
+            store8((bf16 *)ep.out + (size_t)mg * N + n, v);
+        }
     } else if constexpr (EPI == EPI_RESID) {
         float4 *r = (float4 *)(ep.resid + (size_t)mg * N + n);
         float4 x0 = r[0], x1 = r[1];
@@ -169,8 +185,8 @@ __device__ __forceinline__ void wait_stages(int later) {
 
 // The MFMAs of one K stage for a wave's TM x TN tiles.  FIRST: the stage is
 // the tile's first, so its first k-step adds to zero instead of acc.
-// SWAP (bf16): the activation tile is the MFMA "A" operand, so a lane holds
-// four consecutive tokens of one output feature (the blocked V layout).
+// SWAP: the activation tile is the MFMA "A" operand, so a lane holds four
+// consecutive tokens of one output feature (the blocked V layout).
 template <bool FIRST, bool FP8, int TM, int TN, int KSTEPS, int BKB, bool SWAP = false>
 __device__ __forceinline__ void mma_stage(const unsigned char *sa, const unsigned char *sw, const int *aoff,
                                           const int *woff, f32x4 (&acc)[TN][TM]) {
@@ -197,8 +213,10 @@ __device__ __forceinline__ void mma_stage(const unsigned char *sa, const unsigne
                 const i32x8 wf = {(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
-                    acc[j][i] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                        wf, af[i], FIRST && ks == 0 ? zero : acc[j][i], 0, 0, 0, 0, 0, 0);
+                    acc[j][i] = SWAP ? __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                                           af[i], wf, FIRST && ks == 0 ? zero : acc[j][i], 0, 0, 0, 0, 0, 0)
+                                     : __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                                           wf, af[i], FIRST && ks == 0 ? zero : acc[j][i], 0, 0, 0, 0, 0, 0);
             }
         } else {
             bf16x8 af[TM], wf[TN];
@@ -220,19 +238,22 @@ __device__ __forceinline__ void mma_stage(const unsigned char *sa, const unsigne
 
 // Epilogue of a V tile of the QKV projection (swapped operands): acc[j][i]
 // holds tokens r0 + 16 i + 4 g + (0..3) (chunk rows) of V feature
-// f0 + 16 j + r16 (head f >> 5, channel f & 31; V bias `bias`); each lane stores its four tokens' values as 8 bytes of
-// the blocked layout (plus the wrapped copies near lon 0 and X).  Rows whose
-// four tokens leave a lat row (X or the state size not a multiple of 4)
-// are stored one by one.
-template <int TM, int TN>
+// f0 + 16 j + r16 (head f >> 5, channel f & 31; V bias `bias`); each lane
+// stores its four tokens' values in the blocked layout (plus the wrapped
+// copies near lon 0 and X): 8 bytes of bf16, or (FP8) 4 e4m3 codes of
+// value * out_mul[2] after the dequantization acc * a_dequant * w_dequant.
+// Rows whose four tokens leave a lat row (X or the state size not a
+// multiple of 4) are stored one by one.
+template <int TM, int TN, bool FP8>
 __device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, const float *bias, int M, int r0, int f0,
                                             const f32x4 (&acc)[TN][TM], int g, int r16) {
     float bv[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j) bv[j] = bias[f0 + 16 * j + r16];
+    const float dq = FP8 ? ep.a_dequant * ep.w_dequant : 1.0f;
+    const float om = FP8 ? ep.out_mul[2] : 1.0f;
     const int X = ep.vX, xp = ep.vxp, YX = ep.vY * ep.vX;
     const bool quad = (X & 3) == 0 && (ep.T & 3) == 0;
-    bf16 *vt = (bf16 *)ep.vt;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
         const int m4 = r0 + 16 * i + 4 * g;
@@ -245,14 +266,26 @@ __device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, const float *bias
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 const int f = f0 + 16 * j + r16;
-                uint2 u;
-                u.x = pack_bf16x2(fmaf(acc[j][i][0], 1.0f, bv[j]), fmaf(acc[j][i][1], 1.0f, bv[j]));
-                u.y = pack_bf16x2(fmaf(acc[j][i][2], 1.0f, bv[j]), fmaf(acc[j][i][3], 1.0f, bv[j]));
-                bf16 *row = vt + v_blocked_offset(ep.vB, ep.vZ, ep.vY, xp, f >> 5, (int)b, (int)z, (int)y, 0, f & 31);
+                const size_t row = v_blocked_offset(ep.vB, ep.vZ, ep.vY, xp, f >> 5, (int)b, (int)z, (int)y, 0, f & 31);
                 const int i0 = (int)x + 4;
-                *(uint2 *)(row + (size_t)(i0 >> 2) * 128) = u;
-                if (i0 - X >= 0) *(uint2 *)(row + (size_t)((i0 - X) >> 2) * 128) = u;
-                if (i0 + X < xp) *(uint2 *)(row + (size_t)((i0 + X) >> 2) * 128) = u;
+                float e[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) e[k] = fmaf(acc[j][i][k], dq, bv[j]);
+                if constexpr (FP8) {
+                    unsigned char *vt = (unsigned char *)ep.vt + row;
+                    const unsigned u = e4m3x4(e[0] * om, e[1] * om, e[2] * om, e[3] * om);
+                    *(unsigned *)(vt + (size_t)(i0 >> 2) * 128) = u;
+                    if (i0 - X >= 0) *(unsigned *)(vt + (size_t)((i0 - X) >> 2) * 128) = u;
+                    if (i0 + X < xp) *(unsigned *)(vt + (size_t)((i0 + X) >> 2) * 128) = u;
+                } else {
+                    bf16 *vt = (bf16 *)ep.vt + row;
+                    uint2 u;
+                    u.x = pack_bf16x2(e[0], e[1]);
+                    u.y = pack_bf16x2(e[2], e[3]);
+                    *(uint2 *)(vt + (size_t)(i0 >> 2) * 128) = u;
+                    if (i0 - X >= 0) *(uint2 *)(vt + (size_t)((i0 - X) >> 2) * 128) = u;
+                    if (i0 + X < xp) *(uint2 *)(vt + (size_t)((i0 + X) >> 2) * 128) = u;
+                }
             }
         } else {
 #pragma unroll
@@ -266,11 +299,24 @@ __device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, const float *bias
 #pragma unroll
                 for (int j = 0; j < TN; ++j) {
                     const int f = f0 + 16 * j + r16;
-                    const bf16 v = (bf16)fmaf(acc[j][i][e], 1.0f, bv[j]);
-                    bf16 *row = vt + v_blocked_offset(ep.vB, ep.vZ, ep.vY, xp, f >> 5, (int)b, (int)z, (int)y, 0, f & 31);
-                    row[(size_t)(i0 >> 2) * 128 + (i0 & 3)] = v;
-                    if (i0 - X >= 0) row[(size_t)((i0 - X) >> 2) * 128 + ((i0 - X) & 3)] = v;
-                    if (i0 + X < xp) row[(size_t)((i0 + X) >> 2) * 128 + ((i0 + X) & 3)] = v;
+                    const float val = fmaf(acc[j][i][e], dq, bv[j]);
+                    const size_t row = v_blocked_offset(ep.vB, ep.vZ, ep.vY, xp, f >> 5, (int)b, (int)z, (int)y, 0, f & 31);
+                    const size_t o0 = (size_t)(i0 >> 2) * 128 + (i0 & 3);
+                    const size_t o1 = (size_t)((i0 - X) >> 2) * 128 + ((i0 - X) & 3);
+                    const size_t o2 = (size_t)((i0 + X) >> 2) * 128 + ((i0 + X) & 3);
+                    if constexpr (FP8) {
+                        unsigned char *vt = (unsigned char *)ep.vt + row;
+                        const unsigned char c = (unsigned char)(e4m3x4(val * om, 0.f, 0.f, 0.f) & 0xffu);
+                        vt[o0] = c;
+                        if (i0 - X >= 0) vt[o1] = c;
+                        if (i0 + X < xp) vt[o2] = c;
+                    } else {
+                        bf16 *vt = (bf16 *)ep.vt + row;
+                        const bf16 c = (bf16)val;
+                        vt[o0] = c;
+                        if (i0 - X >= 0) vt[o1] = c;
+                        if (i0 + X < xp) vt[o2] = c;
+                    }
                 }
             }
         }
@@ -392,8 +438,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
             issue_w(s0);
         }
 
-    // The tiles of this workgroup.  SWAP (the V tiles of a bf16 QKV
-    // projection with ep.vt set; a workgroup's tiles are all V or none):
+    // The tiles of this workgroup.  SWAP (the V tiles of a QKV projection
+    // with ep.vt set; a workgroup's tiles are all V or none):
     // swapped MFMA operands and the blocked-layout epilogue.  The two bodies
     // are separate instantiations, so neither carries the other's registers.
     auto body = [&](auto swap_tag) {
@@ -428,7 +474,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         const int n0 = (rw ? tn0 : tn0 + t) * BN;
         const int mt = rw ? m0 + t * BM : m0;    // first row of this tile
         if constexpr (SWAP) {
-            vt_epilogue<TM, TN>(ep, ep.bias + 2 * ep.C, M, mt + wm * WM, n0 - 2 * ep.C + wn * WN, acc, g, r16);
+            vt_epilogue<TM, TN, FP8>(ep, ep.bias + 2 * ep.C, M, mt + wm * WM, n0 - 2 * ep.C + wn * WN, acc, g, r16);
             if constexpr (!ZSTART) {
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
@@ -440,7 +486,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         // a feature tile never straddles Q/K/V (C is a multiple of BN)
         const int part = epi_qkv(EPI) ? ep.part0 + n0 / ep.C : 0;
         const size_t qkv_base = (size_t)part * ep.H * ep.Mtot * 32;
-        const float qs = part == 0 ? ep.qscale : 1.0f;
+        const float qs = (part == 0 ? ep.qscale : 1.0f) * (epi_qkv(EPI) && ep.out8 ? ep.out_mul[part] : 1.0f);
         // per-row dequantization (fp8) and per-state amax of the outputs
         float dq[TM];
         int srow[TM];
@@ -558,7 +604,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
         }
     }
     };
-    if constexpr (epi_qkv(EPI) && !FP8) {
+    if constexpr (epi_qkv(EPI)) {
         if (ep.vt && tn0 * BN >= 2 * ep.C) {
             body(std::true_type{});
             return;
@@ -713,6 +759,14 @@ hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, Ep
         const char *v = getenv("WM_GEMM_CFG");
         return v ? atoi(v) : -1;
     }();
+    if (epi_qkv(epi) && ep.vt) {
+        if (ep.a_amax) return hipErrorInvalidValue;   // V tiles dequantize with the one scale a_dequant
+        // a workgroup's feature tiles must be all V or none (as in launch_gemm_lds)
+        const bool n256 = N % 256 == 0 && ep.C % 256 == 0;
+        const int per_part = ep.C / (n256 ? 256 : 128);
+        if (n256) return launch_sa<256, 256, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
+        return launch_sa<128, 128, 2, 2, 2, true>(A, W, M, N, K, epi, ep, stream, per_part % 2 ? 1 : 2, 0);
+    }
     if (N % 256 == 0 && (!epi_qkv(epi) || ep.C % 256 == 0) && cfg != 0) {
         // N = 512 (MLP2 at C = 512): row walk, as in launch_gemm_lds
         if (N == 512) return launch_sa<256, 256, 4, 2, 1, true>(A, W, M, N, K, epi, ep, stream, 2, 1);

@@ -246,7 +246,7 @@ hipError_t launch_nat(const NatArgs &a, bool bf16in, hipStream_t stream) {
 }
 
 hipError_t launch_nat_generic(const NatArgs &a, bool bf16in, hipStream_t stream) {
-    if (a.vt) return hipErrorInvalidValue;     // reads token-major v only
+    if (a.vt || a.q8 || a.o8) return hipErrorInvalidValue;     // reads token-major bf16/f32 q, k, v only
     const long ngroups = (long)((a.Z + GZ - 1) / GZ) * ((a.Y + GY - 1) / GY) * ((a.X + GX - 1) / GX);
     const long waves = ngroups * a.H * a.B;
     if (waves == 0) return hipSuccess;

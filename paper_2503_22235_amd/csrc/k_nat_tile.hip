@@ -787,8 +787,10 @@ __global__ void nat_bias_prep_fp8(NatArgs p) {
 // nat_tile_fp8_kernel (e4m3 QK and PV on 16x16x32 fp8 MFMA, scores in units
 // of c = s_q s_k, per-(state, head) bias table divided by c, e4m3 softmax
 // weights with the static scale 1) on the tiling and level streaming of
-// nat_ring_kernel.  K and V arrive already quantized (kv8 pass): K as e4m3
-// rows of 32 bytes per token, V in the blocked layout with byte elements.
+// nat_ring_kernel.  K and V arrive already quantized (the kv8 pass, or the
+// FP8 QKV projection): K as e4m3 rows of 32 bytes per token, V in the
+// blocked layout with byte elements; Q in bf16 (quantized here) or, with
+// q8, in e4m3; the output in bf16 or, with o8, as e4m3 codes at v's scale.
 // A level is 10 lat rows of K (16 tokens x 32 bytes, the 16-byte halves of
 // token c in row R swapped when bit 1 of R is set, against bank conflicts)
 // and 10 of V (512 bytes), 10 KB; two slots alternate.  Reference: each
@@ -846,7 +848,7 @@ __global__ __launch_bounds__(256, 3) void nat_ring_fp8_kernel(NatArgs p, TileDiv
     clamp_range(y0, TY, p.Y, KY, ylo, yn);
 
     const unsigned char *k8 = (const unsigned char *)p.k + (size_t)b * p.bs + (size_t)h * p.hs;
-    const bf16 *qb = (const bf16 *)p.q + (size_t)b * p.bs + (size_t)h * p.hs;
+    const size_t qoff = (size_t)b * p.bs + (size_t)h * p.hs;   // elements (bf16) or bytes (q8)
     const float aq = p.amax[(size_t)b * p.amax_stride], ak = p.amax[(size_t)b * p.amax_stride + 1],
                 av = p.amax[(size_t)b * p.amax_stride + 2];
     const float c = dq_scale(aq) * dq_scale(ak) * p.qscale;     // score unit, log2 domain
@@ -947,7 +949,8 @@ __global__ __launch_bounds__(256, 3) void nat_ring_fp8_kernel(NatArgs p, TileDiv
         act[G] = zq < p.Z && yq < p.Y && xp_ < p.X - SX;
         const int xc = xp_ < 0 ? xp_ + p.X : (xp_ >= p.X ? xp_ - p.X : xp_);
         qtok[G] = (long)mul24(mul24((unsigned)zc, (unsigned)p.Y) + (unsigned)yc, (unsigned)p.X) + xc;
-        const uint2 q8 = bf16x8_to_e4m3(*(const uint4 *)(qb + qtok[G] * p.ts + 8 * g), mulq);
+        const uint2 q8 = p.q8 ? *(const uint2 *)((const unsigned char *)p.q + qoff + qtok[G] * p.ts + 8 * g)
+                              : bf16x8_to_e4m3(*(const uint4 *)((const bf16 *)p.q + qoff + qtok[G] * p.ts + 8 * g), mulq);
         qf[G] = (long)(((unsigned long long)q8.y << 32) | q8.x);
         const uint2 ks = *(const uint2 *)(k8 + qtok[G] * p.ts + 8 * g);
         mref[G] = xsum16_32(e4m3_dot4(q8.y, ks.y, e4m3_dot4(q8.x, ks.x, 0.f)));                     // the query's own score, raw units (bias below)
@@ -1073,19 +1076,25 @@ __global__ __launch_bounds__(256, 3) void nat_ring_fp8_kernel(NatArgs p, TileDiv
         __syncthreads();
     }
 
-    const float sv = dq_scale(av);
+    // o = s_v (sum p v8) / (sum p); as e4m3 codes at v's scale: (sum p v8) / (sum p)
+    const float sv = p.o8 ? 1.0f : dq_scale(av);
 #pragma unroll
     for (int G = 0; G < 2; ++G) {
         if (!act[G]) continue;
         const float inv = sv / lacc[G][0];
-        bf16 *ob = (bf16 *)p.out + (size_t)b * p.obs + (size_t)qtok[G] * p.ots + h * 32;
+        const size_t oo = (size_t)b * p.obs + (size_t)qtok[G] * p.ots + h * 32;
 #pragma unroll
         for (int tt = 0; tt < 2; ++tt) {
             f32x4 v = oacc[G][tt];
-            uint2 u;
-            u.x = pack_bf16x2(v[0] * inv, v[1] * inv);
-            u.y = pack_bf16x2(v[2] * inv, v[3] * inv);
-            *(uint2 *)(ob + 16 * tt + 4 * g) = u;
+            if (p.o8) {
+                *(unsigned *)((unsigned char *)p.out + oo + 16 * tt + 4 * g) =
+                    e4m3x4(v[0] * inv, v[1] * inv, v[2] * inv, v[3] * inv);
+            } else {
+                uint2 u;
+                u.x = pack_bf16x2(v[0] * inv, v[1] * inv);
+                u.y = pack_bf16x2(v[2] * inv, v[3] * inv);
+                *(uint2 *)((bf16 *)p.out + oo + 16 * tt + 4 * g) = u;
+            }
         }
     }
 }
@@ -1595,6 +1604,7 @@ hipError_t launch_ring_fp8(const NatArgs &a, hipStream_t stream) {
 template <int KZ, int KY, int KX>
 hipError_t launch_tile(const NatArgs &a, hipStream_t stream) {
     if (a.amax && a.vt) return launch_ring_fp8<KZ, KY, KX>(a, stream);
+    if (a.q8 || a.o8) return hipErrorInvalidValue;   // e4m3 q / o: the level-ring kernel only
     if (a.amax) return launch_tile_fp8<KZ, KY, KX>(a, stream);
     if (a.vt) {
         if (a.qscale == 1.0f) return launch_ring<KZ, KY, KX, true>(a, stream);

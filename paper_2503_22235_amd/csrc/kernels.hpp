@@ -77,6 +77,12 @@ struct EpiArgs {
     void *vt;
     int vB, vZ, vY, vX, vxp;
     UDiv dT, dYX, dX;
+    // FP8 GEMMs (EPI_QKV / EPI_GELU): out8 set stores e4m3 codes of each
+    // output value times out_mul[part] (QKV part 0 Q, 1 K, 2 V; GELU part 0)
+    // instead of bf16: the Q/K planes and the blocked V with byte elements,
+    // the GELU output as [M][N] bytes.
+    int out8;
+    float out_mul[3];
 };
 // Rotary position embedding of cnt consecutive channels e.. (e even) of a
 // q or k head row at global row mg (token mg mod T): channel pair p =
@@ -169,6 +175,11 @@ struct NatArgs {
     // or (amax set) e4m3 bytes from launch_kv8 with k in e4m3 as well
     int vt;
     int xp;
+    // e4m3 level-ring kernel (amax and vt set): q8 set, q holds e4m3 codes
+    // (same strides, in bytes) instead of bf16; o8 set, out receives e4m3
+    // codes at v's scale (the output is a convex combination of v rows, so
+    // v's amax bounds it) instead of bf16.
+    int q8, o8;
 };
 // Blocked V layout (bf16), written by the QKV projection of bf16
 // processors for the tiled attention kernel: per (head, state, level, lat)

@@ -9,22 +9,21 @@ namespace wm {
 
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// FP8 block: the region of the e4m3 MLP hidden state, which also holds the
-// e4m3 k and blocked v of the attention before it (M C + B Z Y xp C bytes).
-static size_t fp8_h8_bytes(const wm_processor *p, int B) {
+// FP8 block: the region of the e4m3 q and k planes and the blocked e4m3 v,
+// which later holds the e4m3 GELU output [M][F].
+static size_t fp8_big_bytes(const wm_processor *p, int B) {
     const size_t M = (size_t)B * p->g.Z * p->g.Y * p->g.X;
     const size_t C = p->g.C, F = C * p->mlp;
-    const size_t kv = al256(M * C) + (size_t)B * p->g.Z * p->g.Y * v_blocked_xp(p->g.X) * C;
-    return al256(std::max(M * F, kv));
+    const size_t qkv = al256(2 * M * C) + (size_t)B * p->g.Z * p->g.Y * v_blocked_xp(p->g.X) * C;
+    return al256(std::max(qkv, M * F));
 }
 
 size_t block_workspace_bytes(const wm_processor *p, int B) {
     const size_t M = (size_t)B * p->g.Z * p->g.Y * p->g.X;
     const size_t C = p->g.C, F = C * p->mlp;
     if (p->prec == WM_FP8_E4M3) {
-        // u8/w8 | qkv or h (bf16) | o (bf16) | h8, or k8 and blocked v8 | bias tables | amax slots
-        return al256(M * C) + al256(M * std::max(3 * C, F) * 2) + al256(M * C * 2) + fp8_h8_bytes(p, B) +
-               (size_t)B * p->g.heads * NAT_TBL_WS_FLOATS * 4 + (size_t)AMAX_SHARDS * AMAX_STRIDE * 4;
+        // LN codes | q8 k8 v8, then GELU codes | o8 | bias tables
+        return al256(M * C) + fp8_big_bytes(p, B) + al256(M * C) + (size_t)B * p->g.heads * NAT_TBL_WS_FLOATS * 4;
     }
     const size_t esz = p->prec == WM_BF16 ? 2 : 4;
     const size_t big = (3 * C > F ? 3 * C : F);
@@ -193,26 +192,27 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
 }
 
 // FP8 block: LayerNorms quantize their outputs per state (two passes), the
-// QKV and MLP GEMMs run on e4m3 operands (per-tensor weight scales, per-state
-// activation scales), the QKV and MLP1 epilogues record per-state amax of
-// their bf16 outputs; attention quantizes Q, K and V with those per-state
-// scales and runs QK and PV on e4m3 (weights with the static scale 1); the
-// GELU output is quantized before MLP2; the output projection runs in bf16;
-// softmax, LayerNorm statistics and the residual stream stay float32.
+// Every GEMM and both attention contractions run on e4m3 operands with
+// static per-tensor scales fixed at processor creation from the weights
+// (BlockWeights): each producer stores e4m3 codes directly -- the
+// LayerNorms, the QKV projection (q and k planes, v in the blocked
+// layout), the attention (its output at v's scale) and MLP1 (the GELU
+// output) -- and each consumer dequantizes its MFMA sums with the product
+// of the two scales.  Softmax, LayerNorm statistics and the residual stream
+// stay float32.
 static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s) {
     const wm_grid &g = p->g;
     const BlockWeights &w = p->blk[block];
     const long T = (long)g.Z * g.Y * g.X;
     const int M = (int)(B * T);
     const int C = g.C, F = C * p->mlp, H = g.heads;
-    char *base = (char *)ctx->ws;
-    unsigned char *act8 = (unsigned char *)base;
-    char *big = base + al256((size_t)M * C);
-    char *obuf = big + al256((size_t)M * std::max(3 * C, F) * 2);
-    unsigned char *h8 = (unsigned char *)(obuf + al256((size_t)M * C * 2));
-    float *tbl_ws = (float *)((char *)h8 + fp8_h8_bytes(p, B));
-    unsigned *amax = (unsigned *)((char *)tbl_ws + (size_t)B * H * NAT_TBL_WS_FLOATS * 4);
-    unsigned *amax_qkv = amax + B, *amax_h = amax + 5 * B;
+    const int xp = v_blocked_xp(g.X);
+    unsigned char *act8 = (unsigned char *)ctx->ws;
+    unsigned char *big = act8 + al256((size_t)M * C);
+    unsigned char *q8 = big, *k8 = big + (size_t)M * C, *v8 = big + al256(2 * (size_t)M * C);
+    unsigned char *h8 = big;                                 // after the attention
+    unsigned char *o8 = big + fp8_big_bytes(p, B);
+    float *tbl_ws = (float *)(o8 + al256((size_t)M * C));
     hipError_t e;
     int rc;
 #define WM_TIMED(kind, call, what)                                  \
@@ -220,37 +220,38 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
     if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
     if (B > 64) return fail(WM_EINVAL, "FP8 processors take at most 64 states per call");
-    if (!fp8_attention_applies(&g, B, 32)) return fail(WM_EINVAL, "no e4m3 attention kernel for this grid and batch");
-    if ((e = launch_zero_u32(amax, (size_t)AMAX_SHARDS * AMAX_STRIDE, s)) != hipSuccess)
-        return hip_fail(e, "amax reset");
+    if (!fp8_ring_applies(&g, B)) return fail(WM_EINVAL, "no e4m3 attention kernel for this grid and batch");
     WM_TIMED(PK_LN1, launch_layernorm_fp8_static(x, w.ln1_g, w.ln1_b, M, C, 1e-5f, w.ln1_amax, act8, s), "LN1")
     EpiArgs ep{};
     ep.bias = w.b_qkv;
-    ep.out = big;
+    ep.out = q8;
     ep.C = C;
     ep.H = H;
     ep.qscale = LOG2E / std::sqrt(32.0f);
     ep.a_dequant = w.ln1_amax_h / 448.0f;   // static scale of the LN1 codes
     ep.w_dequant = w.dq_qkv;
     ep.T = T;
-    ep.out_amax = amax_qkv;
-    ep.amax_stride = 3;
-    ep.perm = 1;   // W_qkv and W_1 are stored with permuted rows (perm_row)
+    ep.perm = 1;   // W_qkv (Q and K rows) and W_1 are stored with permuted rows (perm_row)
+    ep.out8 = 1;
+    for (int part = 0; part < 3; ++part) ep.out_mul[part] = 448.0f / w.qkv_amax_h[part];
+    ep.vt = v8;
+    ep.vB = B; ep.vZ = g.Z; ep.vY = g.Y; ep.vX = g.X; ep.vxp = xp;
+    ep.dT = udiv_make((unsigned)T);
+    ep.dYX = udiv_make((unsigned)(g.Y * g.X));
+    ep.dX = udiv_make((unsigned)g.X);
     if (p->rope_tab) {
         ep.rope = p->rope_tab;
         ep.rZ = g.Z; ep.rY = g.Y; ep.rX = g.X;
     }
     WM_TIMED(PK_QKV, launch_gemm_fp8(act8, w.w_qkv, M, 3 * C, C, p->rope_tab ? EPI_QKV_ROPE : EPI_QKV, ep, s), "QKV")
-    if ((e = launch_amax_fold(amax_qkv, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
     NatArgs na{};
-    const size_t plane = (size_t)H * M * 32 * 2;
-    na.q = big;
-    na.k = big + plane;
-    na.v = big + 2 * plane;
+    na.q = q8;
+    na.k = k8;
+    na.v = v8;
     na.bs = T * 32;
     na.ts = 32;
     na.hs = (long)M * 32;
-    na.out = obuf;
+    na.out = o8;
     na.obs = T * C;
     na.ots = C;
     na.rpb = w.rpb_log2;
@@ -259,45 +260,35 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     na.B = B; na.Z = g.Z; na.Y = g.Y; na.X = g.X; na.H = H;
     na.Kz = g.Kz; na.Ky = g.Ky; na.Kx = g.Kx; na.periodic = g.periodic_mask;
     na.tbl_ws = tbl_ws;
-    na.amax = (const float *)amax_qkv;
-    na.amax_stride = 3;
-    // the e4m3 ring kernel: k and v quantized once into the h8 region (free
-    // until MLP1), v in the blocked layout; timed with the attention
-    auto attention = [&]() -> hipError_t {
-        NatArgs nr = na;
-        nr.vt = 1;
-        nr.xp = v_blocked_xp(g.X);
-        const size_t lds = nat_tile_lds_bytes(nr);
-        if (lds == 0 || lds > 160 * 1024) return launch_nat(na, true, s);
-        unsigned char *k8 = h8, *v8 = h8 + al256((size_t)M * C);
-        hipError_t err = launch_kv8(nr, k8, v8, s);
-        if (err != hipSuccess) return err;
-        nr.k = k8;
-        nr.v = v8;
-        return launch_nat(nr, true, s);
-    };
-    WM_TIMED(PK_NA, attention(), "NA")
+    na.amax = w.qkv_amax;      // the static (aq, ak, av) of every state
+    na.amax_stride = 0;
+    na.vt = 1;
+    na.xp = xp;
+    na.q8 = 1;
+    na.o8 = 1;
+    WM_TIMED(PK_NA, launch_nat(na, true, s), "NA")
     EpiArgs er{};
     er.bias = w.b_o;
     er.resid = x;
-    WM_TIMED(PK_PROJ, launch_gemm(obuf, w.w_o, M, C, C, true, EPI_RESID, er, s), "proj")
+    er.a_dequant = w.qkv_amax_h[2] / 448.0f;   // o is coded at v's scale
+    er.w_dequant = w.dq_o;
+    er.T = T;
+    WM_TIMED(PK_PROJ, launch_gemm_fp8(o8, w.w_o, M, C, C, EPI_RESID, er, s), "proj")
     WM_TIMED(PK_LN2, launch_layernorm_fp8_static(x, w.ln2_g, w.ln2_b, M, C, 1e-5f, w.ln2_amax, act8, s), "LN2")
     EpiArgs eg{};
     eg.bias = w.b_1;
-    eg.out = big;
+    eg.out = h8;
     eg.a_dequant = w.ln2_amax_h / 448.0f;   // static scale of the LN2 codes
     eg.w_dequant = w.dq_1;
     eg.T = T;
-    eg.out_amax = amax_h;
-    eg.amax_stride = 1;
     eg.perm = 1;
+    eg.out8 = 1;
+    eg.out_mul[0] = 448.0f / w.h_amax_h;
     WM_TIMED(PK_MLP1, launch_gemm_fp8(act8, w.w_1, M, F, C, EPI_GELU, eg, s), "MLP1")
-    if ((e = launch_amax_fold(amax_h, B, s)) != hipSuccess) return hip_fail(e, "amax fold");
-    WM_TIMED(PK_QUANT, launch_quant_rows(big, M, F, (int)T, (const float *)amax_h, h8, s), "quantize h")
     EpiArgs e2{};
     e2.bias = w.b_2;
     e2.resid = x;
-    e2.a_amax = (const float *)amax_h;
+    e2.a_dequant = w.h_amax_h / 448.0f;
     e2.w_dequant = w.dq_2;
     e2.T = T;
     WM_TIMED(PK_MLP2, launch_gemm_fp8(h8, w.w_2, M, C, F, EPI_RESID, e2, s), "MLP2")

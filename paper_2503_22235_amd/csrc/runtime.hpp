@@ -15,15 +15,27 @@ namespace wm {
 struct BlockWeights {
     const float *ln1_g, *ln1_b, *b_qkv, *rpb_log2, *b_o, *ln2_g, *ln2_b, *b_1, *b_2;
     const void *w_qkv, *w_o, *w_1, *w_2;   // [out][in], processor precision
-    // FP8 processors: w_qkv, w_1, w_2 hold e4m3 codes with these per-tensor
-    // dequantization scales (amax / 448); w_o stays bfloat16.
-    float dq_qkv = 1.f, dq_1 = 1.f, dq_2 = 1.f;
-    // FP8 processors: static amax of each LayerNorm output (device float and
-    // its host copy): a LayerNorm output is bounded by
-    // max_c |gamma_c| sqrt(C - 1) + |beta_c| (the normalized values of a row
-    // have mean 0 and mean square 1, so none exceeds sqrt(C - 1)).
+    // FP8 processors: the four weight matrices hold e4m3 codes with these
+    // per-tensor dequantization scales (amax / 448).
+    float dq_qkv = 1.f, dq_o = 1.f, dq_1 = 1.f, dq_2 = 1.f;
+    // FP8 processors: static amax (scale = amax / 448) of every activation
+    // tensor, bounds that no input can exceed, from the weights alone:
+    //  - LayerNorm output channel c: |gamma_c| sqrt(C - 1) + |beta_c| (a
+    //    normalized row has mean 0 and mean square 1, so no entry exceeds
+    //    sqrt(C - 1)); ln*_amax is the maximum over c (device float and host
+    //    copy);
+    //  - projection output j: sum_c |W_jc| L_c + |b_j| with L_c the bound of
+    //    its LayerNorm input channel; q stored times its score factor; q and
+    //    k times sqrt 2 (rotary, which may be set later, mixes a channel pair);
+    //    qkv_amax = (aq, ak, av) on the device, qkv_amax_h on the host;
+    //  - attention output: a convex combination of v rows, bounded by av;
+    //  - GELU output: max(U, 0.17) for pre-activation bound U (GELU(u) lies
+    //    in [-0.17, max(u, 0)]).
     const float *ln1_amax = nullptr, *ln2_amax = nullptr;
     float ln1_amax_h = 0.f, ln2_amax_h = 0.f;
+    const float *qkv_amax = nullptr;
+    float qkv_amax_h[3] = {0.f, 0.f, 0.f};
+    float h_amax_h = 0.f;
     // BF16 processors: the tiled attention kernel's bias table of this
     // block, prepared once at creation (null: prepared per launch)
     float *nat_tbl = nullptr;
@@ -70,6 +82,9 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int ctx_reserve(wm_ctx *ctx, size_t bytes);
 bool fp8_attention_applies(const wm_grid *g, int B, long ts);
+// Whether the e4m3 level-ring attention of FP8 processors (q and k planes
+// with token stride 32, v in the blocked layout) covers grid g at batch B.
+bool fp8_ring_applies(const wm_grid *g, int B);
 // wm_nat_forward in two parts: argument checks (and the scratch bytes
 // needed), then the launches with the scratch at a given device address.
 // blocked_v: bf16 attention copies v to the blocked layout in the scratch
