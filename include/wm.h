@@ -88,9 +88,9 @@ void wm_ctx_destroy(wm_ctx *ctx);
  * bracketed by HIP events recorded on the stream it is launched on.
  * wm_prof_collect waits for the recorded events, ADDS each kernel kind's
  * total milliseconds and launch count into ms[kind] and counts[kind]
- * (kinds 0..7: LN1, QKV projection, neighborhood attention, output
- * projection, LN2, MLP1, MLP2, FP8 quantization of the MLP hidden state;
- * arrays of nkinds entries, either may be NULL) and clears the records. */
+ * (kinds 0..6: LN1, QKV projection, neighborhood attention, output
+ * projection, LN2, MLP1, MLP2; arrays of nkinds entries, either may be
+ * NULL) and clears the records. */
 int wm_prof_enable(wm_ctx *ctx, int on);
 /* Like wm_prof_enable, for the kinds whose bit is set in kinds_mask only
  * (bit k = kind k; 0 turns timing off), so that a timed region carries
@@ -191,12 +191,20 @@ int wm_linear_fp8(int M, int N, int K, const void *a8, float a_dequant,
  * The library copies and converts what it needs (the host array may be
  * freed on return) and owns the device copy until wm_processor_destroy.
  * Requires d = C/heads = 32 and C in {128, 256, 512, 1024}.
- * WM_FP8_E4M3 processors store the QKV and MLP matrices as e4m3 with
- * per-tensor scales (amax / 448) and quantize the LayerNorm outputs, the
- * GELU output and q, k, v per state and per tensor (dynamic amax / 448);
- * the attention's QK and PV products run on those e4m3 codes and the output
- * projection runs in bfloat16.  The e4m3 attention exists for a lon-periodic
- * grid (periodic_mask 4), a 5x7x7, 3x5x5 or 3x3x3 window and X >= Kx + 7;
+ * WM_FP8_E4M3 processors store all four weight matrices as e4m3 with
+ * per-tensor scales (amax / 448) and run every GEMM and both attention
+ * contractions on e4m3 codes with float32 accumulation.  The activations
+ * (LayerNorm outputs, q, k, v, the attention output, the GELU output) are
+ * quantized with static per-tensor scales bound / 448, where each bound is
+ * computed here from the weights and no input can exceed it: channel c of a
+ * LayerNorm output is at most |gamma_c| sqrt(C-1) + |beta_c|; output j of
+ * a projection is at most sum_c |W_cj| L_c + |b_j| over the bounds L_c of
+ * its input (q and k times sqrt 2, which also covers rotary; q times its
+ * score factor 1/sqrt(32)); the attention output is bounded by v's bound;
+ * the GELU output by max(U, 0.17) for its pre-activation bound U.
+ * Softmax, LayerNorm statistics and the residual stream stay float32.  The
+ * e4m3 attention exists for a lon-periodic grid (periodic_mask 4), a 5x7x7,
+ * 3x5x5 or 3x3x3 window and X >= Kx + 7;
  * an FP8 processor on any other grid is rejected with WM_EINVAL (checked
  * before the context, so no device is needed to be told).  BF16 processors also prepare each block's
  * attention bias table on the device here.  Returns once the upload (and

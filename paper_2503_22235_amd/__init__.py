@@ -99,7 +99,7 @@ _SIGS = {
     "wm_prof_collect": (_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong), _int]),
 }
 
-PROF_KINDS = ("ln1", "qkv", "nat", "proj", "ln2", "mlp1", "mlp2", "quant")
+PROF_KINDS = ("ln1", "qkv", "nat", "proj", "ln2", "mlp1", "mlp2")
 
 
 def lib():

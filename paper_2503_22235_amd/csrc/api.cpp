@@ -68,11 +68,11 @@ bool fp8_attention_applies(const wm_grid *g, int B, long ts) {
     return lds > 0 && lds <= 160 * 1024;
 }
 
-bool fp8_ring_applies(const wm_grid *g, int B) {
+bool fp8_ring_applies(const wm_grid *g, int B, long ts) {
     static float dummy_tbl;
     static float dummy_amax;
     NatArgs a{};
-    a.ts = 32;
+    a.ts = ts;
     a.B = B; a.Z = g->Z; a.Y = g->Y; a.X = g->X; a.H = g->heads;
     a.Kz = g->Kz; a.Ky = g->Ky; a.Kx = g->Kx; a.periodic = g->periodic_mask;
     a.tbl_ws = &dummy_tbl;       // only tested for null
@@ -97,6 +97,8 @@ bool ring_attention_applies(const wm_grid *g, int B, long ts) {
     const size_t lds = nat_tile_lds_bytes(a);
     return lds > 0 && lds <= 160 * 1024;
 }
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 int ctx_reserve(wm_ctx *ctx, size_t bytes) {
     if (bytes <= ctx->ws_bytes) return WM_OK;
@@ -132,6 +134,9 @@ int nat_forward_check(const wm_grid *g, int B, wm_precision prec, const void *q,
                (fp8 ? (size_t)AMAX_SHARDS * AMAX_STRIDE * 4 : 0);
     if (blocked_v && prec == WM_BF16 && B > 0 && ring_attention_applies(g, B, g->C))
         *ws_need += (size_t)B * g->Z * g->Y * v_blocked_xp(g->X) * g->C * 2;
+    if (blocked_v && fp8 && B > 0 && fp8_ring_applies(g, B, g->C))   // e4m3 k, then blocked e4m3 v
+        *ws_need = al256(*ws_need) + al256((size_t)B * g->Z * g->Y * g->X * g->C) +
+                   (size_t)B * g->Z * g->Y * v_blocked_xp(g->X) * g->C;
     if (B == 0) return WM_OK;
     if (!q || !k || !v || !rpb || !out) return fail(WM_EINVAL, "NULL tensor");
     if (fp8 && !fp8_attention_applies(g, B, g->C))
@@ -168,6 +173,18 @@ int nat_forward_into(const wm_grid *g, int B, wm_precision prec, const void *q, 
         if ((e = launch_amax_fold(amax, 3 * B, s)) != hipSuccess) return hip_fail(e, "amax fold");
         a.amax = (const float *)amax;
         a.amax_stride = 3;
+    }
+    if (blocked_v && fp8 && fp8_ring_applies(g, B, g->C)) {
+        // k and v quantized once (k with its strides, v in the blocked layout,
+        // after the tables and amax slots), read by the e4m3 level-ring kernel
+        const size_t off = al256(tbl_bytes + (size_t)AMAX_SHARDS * AMAX_STRIDE * 4);
+        unsigned char *k8 = (unsigned char *)ws + off;
+        unsigned char *v8 = k8 + al256((size_t)B * T * g->C);
+        a.xp = v_blocked_xp(g->X);
+        a.vt = 1;
+        if ((e = launch_kv8(a, k8, v8, s)) != hipSuccess) return hip_fail(e, "k, v to e4m3");
+        a.k = k8;
+        a.v = v8;
     }
     if (blocked_v && prec == WM_BF16 && ring_attention_applies(g, B, g->C)) {
         // v copied to the blocked layout (after the tables), read by the level-ring kernel
@@ -355,7 +372,7 @@ int wm_processor_create(wm_ctx *ctx, const wm_grid *g, int n_blocks, int mlp_rat
     if (prec != WM_F32 && prec != WM_BF16 && prec != WM_FP8_E4M3)
         return fail(WM_EINVAL, "processor precision %d not supported", (int)prec);
     // (head-major q, k, v: 32 elements per token)
-    if (prec == WM_FP8_E4M3 && !fp8_ring_applies(g, 1))
+    if (prec == WM_FP8_E4M3 && !fp8_ring_applies(g, 1, 32))
         return fail(WM_EINVAL, "FP8 processors run QK and PV on e4m3 codes, which needs lon-periodic only "
                                "(periodic_mask 4), a 5x7x7, 3x5x5 or 3x3x3 window and lon >= 8 + Kx - 1");
     if (!host_params) return fail(WM_EINVAL, "host_params is NULL");

@@ -14,53 +14,7 @@ namespace {
 
 __device__ __forceinline__ float clamp448(float v) { return fminf(fmaxf(v, -448.0f), 448.0f); }
 
-// Four floats -> four e4m3 codes (byte i = value i), round to nearest even.
-__device__ __forceinline__ unsigned pack4_fp8(float a, float b, float c, float d) {
-    unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(a), clamp448(b), 0, false);
-    return (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(c), clamp448(d), (int)w, true);
-}
-
 __device__ __forceinline__ float inv_scale(float amax) { return amax > 0.f ? 448.0f / amax : 1.0f; }
-
-// Pass 1 of an FP8 LayerNorm: per-state amax of the LN output.
-template <int VPT>
-__global__ __launch_bounds__(256) void ln_amax_kernel(const float *__restrict__ x, const float *__restrict__ gamma,
-                                                      const float *__restrict__ beta, int M, int T, float eps,
-                                                      unsigned *__restrict__ amax) {
-    constexpr int C = VPT * 64;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= M) return;
-    const int lane = threadIdx.x & 63;
-    const float *xr = x + (size_t)row * C;
-    float v[VPT];
-#pragma unroll
-    for (int j = 0; j < VPT / 2; ++j) {
-        const float2 t = *(const float2 *)(xr + 2 * (j * 64 + lane));
-        v[2 * j] = t.x;
-        v[2 * j + 1] = t.y;
-    }
-    float s = 0.f;
-#pragma unroll
-    for (int i = 0; i < VPT; ++i) s += v[i];
-    const float mean = wave_sum(s) * (1.0f / C);
-    float q = 0.f;
-#pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-        const float d = v[i] - mean;
-        q = fmaf(d, d, q);            // explicit: both passes get the same statistics
-    }
-    const float rstd = 1.0f / sqrtf(wave_sum(q) * (1.0f / C) + eps);
-    float m = 0.f;
-#pragma unroll
-    for (int j = 0; j < VPT / 2; ++j)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int c = 2 * (j * 64 + lane) + u;
-            m = fmaxf(m, fabsf(fmaf((v[2 * j + u] - mean) * rstd, gamma[c], beta[c])));
-        }
-    m = wave_max(m);
-    if (lane == 0) atomicMax(amax + (blockIdx.x % AMAX_SHARDS) * AMAX_STRIDE + row / T, __float_as_uint(m));
-}
 
 // Fold the shard copies of n amax slots into shard 0.
 __global__ void amax_fold_kernel(unsigned *amax, int n) {
@@ -71,7 +25,8 @@ __global__ void amax_fold_kernel(unsigned *amax, int n) {
     amax[i] = m;
 }
 
-// Pass 2: LayerNorm, then quantize with the state's scale.
+// LayerNorm, then quantize with the scale of each row's state (one scale
+// for every row when T = M).
 template <int VPT>
 __global__ __launch_bounds__(256) void ln_quant_kernel(const float *__restrict__ x, const float *__restrict__ gamma,
                                                        const float *__restrict__ beta, int M, int T, float eps,
@@ -113,33 +68,6 @@ __global__ __launch_bounds__(256) void ln_quant_kernel(const float *__restrict__
     }
 }
 
-// bf16 rows [M][F] -> e4m3 with the scale of each row's state.  One wave per
-// row (the state is looked up once), 8 values per lane per step.
-__global__ __launch_bounds__(256) void quant_rows_kernel(const bf16 *__restrict__ in, int M, int F, int T,
-                                                         const float *__restrict__ amax,
-                                                         unsigned char *__restrict__ out) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= M) return;
-    const int lane = threadIdx.x & 63;
-    const float inv = inv_scale(amax[row / T]);
-    const bf16 *src = in + (size_t)row * F;
-    unsigned char *dst = out + (size_t)row * F;
-    for (int c = 8 * lane; c < F; c += 512) {
-        const uint4 u = *(const uint4 *)(src + c);
-        const unsigned w[4] = {u.x, u.y, u.z, u.w};
-        float f[8];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            f[2 * q] = bf_bits2f((unsigned short)(w[q] & 0xffff)) * inv;
-            f[2 * q + 1] = bf_bits2f((unsigned short)(w[q] >> 16)) * inv;
-        }
-        uint2 o;
-        o.x = pack4_fp8(f[0], f[1], f[2], f[3]);
-        o.y = pack4_fp8(f[4], f[5], f[6], f[7]);
-        *(uint2 *)(dst + c) = o;
-    }
-}
-
 // float32 -> e4m3 with one given multiplier (codes = RNE(clamp(x * mul))).
 __global__ __launch_bounds__(256) void quant_f32_kernel(const float *__restrict__ in, size_t n, float mul,
                                                         unsigned char *__restrict__ out) {
@@ -175,17 +103,6 @@ __global__ void zero_u32_kernel(unsigned *p, size_t n) {
 }
 
 template <int VPT>
-hipError_t ln_fp8(const float *x, const float *g, const float *b, int M, int T, float eps, unsigned *amax,
-                  unsigned char *out, hipStream_t s) {
-    const int grid = (M + 3) / 4;
-    const int nstates = (M + T - 1) / T;
-    ln_amax_kernel<VPT><<<grid, 256, 0, s>>>(x, g, b, M, T, eps, amax);
-    amax_fold_kernel<<<(nstates + 255) / 256, 256, 0, s>>>(amax, nstates);
-    ln_quant_kernel<VPT><<<grid, 256, 0, s>>>(x, g, b, M, T, eps, (const float *)amax, out);
-    return hipGetLastError();
-}
-
-template <int VPT>
 hipError_t ln_fp8_static(const float *x, const float *g, const float *b, int M, float eps, const float *amax,
                          unsigned char *out, hipStream_t s) {
     // one scale for every row: the quantization pass alone (rows / M == 0)
@@ -205,26 +122,6 @@ hipError_t launch_layernorm_fp8_static(const float *x, const float *gamma, const
     case 1024: return ln_fp8_static<16>(x, gamma, beta, M, eps, amax, out, stream);
     default: return hipErrorInvalidValue;
     }
-}
-
-hipError_t launch_layernorm_fp8(const float *x, const float *gamma, const float *beta, int M, int C, int T,
-                                float eps, unsigned *amax, unsigned char *out, hipStream_t stream) {
-    if (M <= 0) return hipSuccess;
-    switch (C) {
-    case 128: return ln_fp8<2>(x, gamma, beta, M, T, eps, amax, out, stream);
-    case 256: return ln_fp8<4>(x, gamma, beta, M, T, eps, amax, out, stream);
-    case 512: return ln_fp8<8>(x, gamma, beta, M, T, eps, amax, out, stream);
-    case 1024: return ln_fp8<16>(x, gamma, beta, M, T, eps, amax, out, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_quant_rows(const void *in_bf16, int M, int F, int T, const float *amax, unsigned char *out,
-                             hipStream_t stream) {
-    if (M <= 0) return hipSuccess;
-    if (F % 8) return hipErrorInvalidValue;
-    quant_rows_kernel<<<(M + 3) / 4, 256, 0, stream>>>((const bf16 *)in_bf16, M, F, T, amax, out);
-    return hipGetLastError();
 }
 
 hipError_t launch_amax_bf16(const void *x, size_t per_state, int B, unsigned *amax, int amax_stride,

@@ -135,17 +135,10 @@ hipError_t launch_amax_bf16(const void *x, size_t per_state, int B, unsigned *am
 // zero n 32-bit words (a kernel, so graph capture records no memset node)
 hipError_t launch_zero_u32(unsigned *p, size_t n, hipStream_t stream);
 hipError_t launch_amax_fold(unsigned *amax, int n, hipStream_t stream);
-// Two-pass LayerNorm: per-state amax of the LN output (atomicMax into
-// amax[state], which the caller zeroes), then LN + quantize.
-hipError_t launch_layernorm_fp8(const float *x, const float *gamma, const float *beta, int M, int C, int T,
-                                float eps, unsigned *amax, unsigned char *out, hipStream_t stream);
 // LayerNorm + quantize with one static amax (device float at `amax`) for
 // every row: a single pass.
 hipError_t launch_layernorm_fp8_static(const float *x, const float *gamma, const float *beta, int M, int C,
                                        float eps, const float *amax, unsigned char *out, hipStream_t stream);
-// bf16 rows [M][F] -> e4m3 with each row's state scale (F % 8 == 0)
-hipError_t launch_quant_rows(const void *in_bf16, int M, int F, int T, const float *amax,
-                             unsigned char *out, hipStream_t stream);
 // float32 -> e4m3 codes = RNE(clamp(x * mul, +-448))
 hipError_t launch_quant_f32(const float *in, size_t n, float mul, unsigned char *out, hipStream_t stream);
 

@@ -220,7 +220,7 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
     if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
     if (B > 64) return fail(WM_EINVAL, "FP8 processors take at most 64 states per call");
-    if (!fp8_ring_applies(&g, B)) return fail(WM_EINVAL, "no e4m3 attention kernel for this grid and batch");
+    if (!fp8_ring_applies(&g, B, 32)) return fail(WM_EINVAL, "no e4m3 attention kernel for this grid and batch");
     WM_TIMED(PK_LN1, launch_layernorm_fp8_static(x, w.ln1_g, w.ln1_b, M, C, 1e-5f, w.ln1_amax, act8, s), "LN1")
     EpiArgs ep{};
     ep.bias = w.b_qkv;

@@ -44,7 +44,7 @@ struct BlockWeights {
 constexpr int MAX_BLOCKS = 64;
 
 // Kernel kinds of a block, in launch order (timing records).
-enum ProfKind : int { PK_LN1 = 0, PK_QKV, PK_NA, PK_PROJ, PK_LN2, PK_MLP1, PK_MLP2, PK_QUANT, PK_N };
+enum ProfKind : int { PK_LN1 = 0, PK_QKV, PK_NA, PK_PROJ, PK_LN2, PK_MLP1, PK_MLP2, PK_N };
 
 struct ProfRec {
     int kind;
@@ -82,9 +82,9 @@ int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int ctx_reserve(wm_ctx *ctx, size_t bytes);
 bool fp8_attention_applies(const wm_grid *g, int B, long ts);
-// Whether the e4m3 level-ring attention of FP8 processors (q and k planes
-// with token stride 32, v in the blocked layout) covers grid g at batch B.
-bool fp8_ring_applies(const wm_grid *g, int B);
+// Whether the e4m3 level-ring attention (v in the blocked layout, q and k
+// with token stride ts) covers grid g at batch B.
+bool fp8_ring_applies(const wm_grid *g, int B, long ts);
 // wm_nat_forward in two parts: argument checks (and the scratch bytes
 // needed), then the launches with the scratch at a given device address.
 // blocked_v: bf16 attention copies v to the blocked layout in the scratch

@@ -1,12 +1,22 @@
 """wm_nat_forward_noalloc (the attention entry point that allocates nothing)
 against wm_nat_forward, through the C ABI.
 
-Both run the same kernels; the no-allocation variant keeps its scratch (bias
-tables, FP8 amax slots) in a fixed device array that every call on the GPU
-shares.  Each precision makes two calls in a row, the second on a smaller
-input, so the second call runs on the scratch the first one left behind.
-The results must be bit-identical to wm_nat_forward's, and the first call of
-each precision is also held to the oracle.
+The no-allocation variant keeps its scratch (bias tables, FP8 amax slots)
+in a fixed device array that every call on the GPU shares.  Each precision
+makes two calls in a row, the second on a smaller input, so the second call
+runs on the scratch the first one left behind.  FP32 and BF16 run the same
+arithmetic as wm_nat_forward (BF16 on token-major v instead of the blocked
+copy wm_nat_forward makes in its workspace, with the same key order) and
+must be bit-identical to it.  FP8: wm_nat_forward quantizes k and v once
+into its workspace for the level-ring kernel, while the no-allocation
+variant (whose scratch holds no copies of k and v) runs the tiled kernel
+that quantizes as it stages.  Both take the same e4m3 codes of q, k and v,
+but the softmax weights are rounded to e4m3 relative to different
+references (the tiled kernel's running maximum, the ring kernel's own
+score of each query), so the two differ by a few e4m3 steps of the
+weights; they are held to each other with the FP8 attention tolerance
+(0.04, the bound against the oracle on quantized operands).  The first
+call of each precision is also held to the oracle (FP8: both entry points).
 """
 import numpy as np
 import pytest
@@ -74,17 +84,25 @@ def test_noalloc_matches_nat_forward(env, prec):
         wm.wm_nat_forward_noalloc(g, B, prec, dev[0], dev[1], dev[2], rpb_d, out_na)
         wm.wm_nat_forward(ctx, g, B, prec, dev[0], dev[1], dev[2], rpb_d, out_ref)
         torch.cuda.synchronize()
-        assert torch.equal(out_na.view(torch.int16 if prec else torch.int32),
-                           out_ref.view(torch.int16 if prec else torch.int32)), (prec, i)
+        got = out_na.float().cpu().numpy()
+        if prec == 2:
+            d = O.rel_l2(got, out_ref.float().cpu().numpy())
+            say(f"  rel_l2 vs wm_nat_forward {d:.3e} (tol 0.04)")
+            assert d <= 0.04, (prec, i)
+        else:
+            assert torch.equal(out_na.view(torch.int16 if prec else torch.int32),
+                               out_ref.view(torch.int16 if prec else torch.int32)), (prec, i)
         if i == 0:
-            got = out_na.float().cpu().numpy()
+            outs = [got]
             if prec == 2:
                 # e4m3 operands: the oracle on q, k, v quantized by its own codec
                 ref = np.stack([O.nat_c(*(_q8(h[b]) for h in host), rpb, g) for b in range(B)])
                 tol = 0.04
+                outs.append(out_ref.float().cpu().numpy())
             else:
                 ref = np.stack([O.nat_c(host[0][b], host[1][b], host[2][b], rpb, g) for b in range(B)])
                 tol = 1e-5 if prec == 0 else 1e-2
-            err = O.rel_l2(got, ref)
-            say(f"  rel_l2 vs oracle {err:.3e} (tol {tol})")
-            assert err <= tol
+            for o in outs:
+                err = O.rel_l2(o, ref)
+                say(f"  rel_l2 vs oracle {err:.3e} (tol {tol})")
+                assert err <= tol
