@@ -525,7 +525,11 @@ def main():
     sys.stderr.flush()
     # Every child process this run started has been waited for and every
     # server thread joined; end here without the interpreter's teardown of
-    # the HIP runtime and its allocations, which can outlast the output.
+    # the HIP runtime and its allocations, which can outlast the output --
+    # except under a profiler, whose tool writes its results from the
+    # process's exit handlers.
+    if any(k.startswith("ROCPROF") for k in os.environ) or "rocprof" in os.environ.get("LD_PRELOAD", ""):
+        sys.exit(0)
     os._exit(0)
 
 
