@@ -25,46 +25,67 @@ __global__ void amax_fold_kernel(unsigned *amax, int n) {
     amax[i] = m;
 }
 
-// LayerNorm, then quantize with the scale of each row's state (one scale
-// for every row when T = M).
-template <int VPT>
-__global__ __launch_bounds__(256) void ln_quant_kernel(const float *__restrict__ x, const float *__restrict__ gamma,
-                                                       const float *__restrict__ beta, int M, int T, float eps,
-                                                       const float *__restrict__ amax, unsigned char *__restrict__ out) {
+// LayerNorm, then e4m3 codes with one static scale amax/448 for every row
+// (`amax`: a device float).  The layout of layernorm_kernel: RPW rows per
+// wave, each lane W consecutive channels per chunk (16-byte loads), so a
+// lane stores its W codes at once.
+template <int VPT, int RPW>
+__global__ __launch_bounds__(256) void ln8_kernel(const float *__restrict__ x, const float *__restrict__ gamma,
+                                                  const float *__restrict__ beta, int M, float eps,
+                                                  const float *__restrict__ amax, unsigned char *__restrict__ out) {
     constexpr int C = VPT * 64;
-    static_assert(VPT % 4 == 0 || VPT == 2, "per-lane chunk");
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= M) return;
+    constexpr int W = VPT >= 4 ? 4 : VPT;     // channels per lane and chunk
+    constexpr int NV = VPT / W;
+    const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
+    if (row0 >= M) return;
     const int lane = threadIdx.x & 63;
-    const float *xr = x + (size_t)row * C;
-    float v[VPT];
+    const float inv = inv_scale(*amax);
+    float v[RPW][VPT];
 #pragma unroll
-    for (int j = 0; j < VPT / 2; ++j) {
-        const float2 t = *(const float2 *)(xr + 2 * (j * 64 + lane));
-        v[2 * j] = t.x;
-        v[2 * j + 1] = t.y;
+    for (int r = 0; r < RPW; ++r) {
+        const float *xr = x + (size_t)min(row0 + r, M - 1) * C;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int base = (j * 64 + lane) * W;
+            if constexpr (W == 4) {
+                const float4 t = *(const float4 *)(xr + base);
+                v[r][4 * j] = t.x; v[r][4 * j + 1] = t.y; v[r][4 * j + 2] = t.z; v[r][4 * j + 3] = t.w;
+            } else {
+                const float2 t = *(const float2 *)(xr + base);
+                v[r][2 * j] = t.x; v[r][2 * j + 1] = t.y;
+            }
+        }
     }
-    float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) s += v[i];
-    const float mean = wave_sum(s) * (1.0f / C);
-    float q = 0.f;
+    for (int r = 0; r < RPW; ++r) {
+        const int row = row0 + r;
+        float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-        const float d = v[i] - mean;
-        q = fmaf(d, d, q);            // explicit: both passes get the same statistics
-    }
-    const float rstd = 1.0f / sqrtf(wave_sum(q) * (1.0f / C) + eps);
-    const float inv = inv_scale(amax[row / T]);
-    unsigned char *o = out + (size_t)row * C;
+        for (int i = 0; i < VPT; ++i) s += v[r][i];
+        const float mean = wave_sum(s) * (1.0f / C);
+        float q = 0.f;
 #pragma unroll
-    for (int j = 0; j < VPT / 2; ++j) {
-        const int c = 2 * (j * 64 + lane);
-        // explicit FMAs: the same value as the amax pass, whatever the contraction
-        const float y0 = fmaf((v[2 * j] - mean) * rstd, gamma[c], beta[c]) * inv;
-        const float y1 = fmaf((v[2 * j + 1] - mean) * rstd, gamma[c + 1], beta[c + 1]) * inv;
-        const unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(y0), clamp448(y1), 0, false);
-        *(unsigned short *)(o + c) = (unsigned short)(w & 0xffffu);
+        for (int i = 0; i < VPT; ++i) {
+            const float d = v[r][i] - mean;
+            q = fmaf(d, d, q);
+        }
+        const float rstd = 1.0f / sqrtf(wave_sum(q) * (1.0f / C) + eps);
+        if (row >= M) continue;
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            const int base = (j * 64 + lane) * W;
+            float y[W];
+            // explicit FMA: the rounding must not depend on the row's slot in
+            // the unrolled row loop (its position depends on the batch)
+#pragma unroll
+            for (int t = 0; t < W; ++t) y[t] = fmaf((v[r][W * j + t] - mean) * rstd, gamma[base + t], beta[base + t]) * inv;
+            unsigned char *o = out + (size_t)row * C + base;
+            const unsigned w = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(y[0]), clamp448(y[1]), 0, false);
+            if constexpr (W == 4)
+                *(unsigned *)o = (unsigned)__builtin_amdgcn_cvt_pk_fp8_f32(clamp448(y[2]), clamp448(y[3]), (int)w, true);
+            else
+                *(unsigned short *)o = (unsigned short)(w & 0xffffu);
+        }
     }
 }
 
@@ -105,8 +126,8 @@ __global__ void zero_u32_kernel(unsigned *p, size_t n) {
 template <int VPT>
 hipError_t ln_fp8_static(const float *x, const float *g, const float *b, int M, float eps, const float *amax,
                          unsigned char *out, hipStream_t s) {
-    // one scale for every row: the quantization pass alone (rows / M == 0)
-    ln_quant_kernel<VPT><<<(M + 3) / 4, 256, 0, s>>>(x, g, b, M, M, eps, amax, out);
+    constexpr int RPW = 2;
+    ln8_kernel<VPT, RPW><<<(M + 4 * RPW - 1) / (4 * RPW), 256, 0, s>>>(x, g, b, M, eps, amax, out);
     return hipGetLastError();
 }
 
