@@ -243,6 +243,18 @@ int wm_processor_block(wm_ctx *ctx, const wm_processor *p, int block, int B,
 int wm_processor_step(wm_ctx *ctx, const wm_processor *p, int B, float *x,
                       void *stream);
 
+/* One processor step (Sec. 2.1) on B states that live in separate device
+ * buffers (the batches of a server whose requests keep their states where
+ * they are, Sec. 2.2 operational use): dev_states is a DEVICE array of B
+ * pointers, each to a float32 [Z][Y][X][C] state, updated in place; the
+ * kernels read and write the residual stream through the pointers, so no
+ * state is copied.  Results are bit-identical to wm_processor_step on the
+ * same states stacked in one buffer.  The array and the states must stay
+ * valid until the step has run on `stream`.  B < 0, B > 64 or a NULL array
+ * -> WM_EINVAL. */
+int wm_processor_step_states(wm_ctx *ctx, const wm_processor *p, int B,
+                             float *const *dev_states, void *stream);
+
 /* Greedy latent-rollout schedule (Sec. 2.1, latent rollout): for
  * lead_hours >= 0 writes floor(L/6) sixes followed by (L mod 6) ones into
  * HOST steps_out (if non-NULL and cap is large enough) and returns the
@@ -265,7 +277,11 @@ int wm_rollout(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
  * on a copy stream while other requests compute.  Every scheduler iteration
  * batches up to max_batch admitted requests whose next processor (six-hour
  * or one-hour, greedy schedule) is the same into one step launch; requests
- * join and leave the batch between steps.  Finished states are copied out
+ * join and leave the batch between steps.  With float32 slots the step runs
+ * on the slots in place (the kernels address the batch's states through a
+ * device array of slot pointers, as wm_processor_step_states); with
+ * bfloat16 slots (half the memory per request) each step converts the
+ * batch's slots into a float32 buffer and back.  Finished states are copied out
  * on the copy stream.  Each request's result does not depend on what it
  * was batched with (every kernel computes a state's tokens the same way
  * whatever the batch).  Calls are thread-safe. */

@@ -16,7 +16,8 @@ __all__ = [
     "WM_F32", "WM_BF16", "WM_FP8_E4M3", "WmError", "wm_grid", "lib",
     "wm_version", "wm_ctx_create", "wm_ctx_destroy", "wm_nat_indices",
     "wm_nat_forward", "wm_layernorm", "wm_linear", "wm_processor_create",
-    "wm_processor_destroy", "wm_processor_block", "wm_processor_step", "wm_processor_set_rope",
+    "wm_processor_destroy", "wm_processor_block", "wm_processor_step", "wm_processor_step_states",
+    "wm_processor_set_rope",
     "wm_schedule", "wm_rollout", "wm_forecast_hourly", "wm_relerr_l2", "grid_of", "LIB_PATH",
     "wm_prof_enable", "wm_prof_select", "wm_prof_collect", "PROF_KINDS", "wm_serve_create",
     "wm_serve_submit", "wm_serve_poll", "wm_serve_status", "wm_serve_destroy",
@@ -82,6 +83,7 @@ _SIGS = {
     "wm_processor_set_rope": (_int, [_vp, _int]),
     "wm_processor_block": (_int, [_vp, _vp, _int, _int, _vp, _vp]),
     "wm_processor_step": (_int, [_vp, _vp, _int, _vp, _vp]),
+    "wm_processor_step_states": (_int, [_vp, _vp, _int, _vp, _vp]),
     "wm_schedule": (_int, [_int, ctypes.POINTER(_int), _int]),
     "wm_rollout": (_int, [_vp, _vp, _vp, _int, _vp, _int, _vp]),
     "wm_forecast_hourly": (_int, [_vp, _vp, _vp, _vp, _int, _vp, _int, _vp]),
@@ -243,6 +245,11 @@ def wm_processor_block(ctx, p, block, B, x, stream=None):
 
 def wm_processor_step(ctx, p, B, x, stream=None):
     return _check(lib().wm_processor_step(ctx.handle, p.handle, B, _ptr(x), _stream(stream)))
+
+
+def wm_processor_step_states(ctx, p, B, dev_states, stream=None):
+    """dev_states: a device tensor (int64) holding B state addresses."""
+    return _check(lib().wm_processor_step_states(ctx.handle, p.handle, B, _ptr(dev_states), _stream(stream)))
 
 
 def wm_schedule(lead_hours: int):

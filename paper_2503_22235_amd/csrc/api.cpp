@@ -309,7 +309,8 @@ int wm_layernorm(int M, int C, const float *x, const float *gamma, const float *
     if (out_prec != WM_F32 && out_prec != WM_BF16) return fail(WM_EINVAL, "out precision must be F32 or BF16");
     if (M == 0) return WM_OK;
     if (!x || !gamma || !beta || !out) return fail(WM_EINVAL, "NULL tensor");
-    hipError_t e = launch_layernorm(x, gamma, beta, out, out_prec == WM_BF16, M, C, eps, (hipStream_t)stream);
+    hipError_t e = launch_layernorm(StateRows{const_cast<float *>(x), nullptr, 0}, gamma, beta, out, out_prec == WM_BF16, M, C,
+                                    eps, (hipStream_t)stream);
     return e == hipSuccess ? WM_OK : hip_fail(e, "layernorm launch");
 }
 
@@ -617,7 +618,7 @@ int wm_processor_block(wm_ctx *ctx, const wm_processor *p, int block, int B, flo
     if (!x) return fail(WM_EINVAL, "x is NULL");
     int rc = reserve_block_workspace(ctx, p, B);
     if (rc) return rc;
-    return run_block(ctx, p, block, B, x, (hipStream_t)stream);
+    return run_block(ctx, p, block, B, x, nullptr, (hipStream_t)stream);
 }
 
 int wm_processor_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, void *stream) {
@@ -627,7 +628,17 @@ int wm_processor_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, void 
     if (!x) return fail(WM_EINVAL, "x is NULL");
     int rc = reserve_block_workspace(ctx, p, B);
     if (rc) return rc;
-    return run_step(ctx, p, B, x, (hipStream_t)stream);
+    return run_step(ctx, p, B, x, nullptr, (hipStream_t)stream);
+}
+
+int wm_processor_step_states(wm_ctx *ctx, const wm_processor *p, int B, float *const *dev_states, void *stream) {
+    if (!ctx || !p) return fail(WM_EINVAL, "NULL ctx or processor");
+    if (B < 0 || B > 64) return fail(WM_EINVAL, "batch %d outside 0..64", B);
+    if (B == 0) return WM_OK;
+    if (!dev_states) return fail(WM_EINVAL, "dev_states is NULL");
+    int rc = reserve_block_workspace(ctx, p, B);
+    if (rc) return rc;
+    return run_step(ctx, p, B, nullptr, dev_states, (hipStream_t)stream);
 }
 
 int wm_schedule(int lead_hours, int *steps_out, int cap) {
@@ -655,7 +666,7 @@ int wm_rollout(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1, int 
     std::vector<int> steps(greedy_schedule(lead_hours, nullptr, 0));
     greedy_schedule(lead_hours, steps.data(), (int)steps.size());
     for (int s : steps) {
-        rc = run_step(ctx, s == 6 ? p6 : p1, B, x, (hipStream_t)stream);
+        rc = run_step(ctx, s == 6 ? p6 : p1, B, x, nullptr, (hipStream_t)stream);
         if (rc) return rc;
     }
     return WM_OK;
@@ -709,7 +720,7 @@ int wm_forecast_hourly(wm_ctx *ctx, const wm_processor *p6, const wm_processor *
         int jmax = 0;
         for (int i = 0; i < nbr; ++i) jmax = std::max(jmax, std::min(5, hours - base[i]));
         for (int j = 1; j <= jmax; ++j) {
-            if ((rc = run_step(ctx, p1, nbr, branch, s))) return rc;
+            if ((rc = run_step(ctx, p1, nbr, branch, nullptr, s))) return rc;
             for (int i = 0; i < nbr; ++i)
                 if (float *o = base[i] + j <= hours ? out_of(base[i] + j) : nullptr)
                     if ((rc = copy(o, branch + (size_t)i * n))) return rc;
@@ -719,7 +730,7 @@ int wm_forecast_hourly(wm_ctx *ctx, const wm_processor *p6, const wm_processor *
     };
     for (int lead = 0; lead <= hours; lead += 6) {
         if (lead > 0) {
-            if ((rc = run_step(ctx, p6, 1, chain, s))) return rc;
+            if ((rc = run_step(ctx, p6, 1, chain, nullptr, s))) return rc;
             if (float *o = out_of(lead))
                 if ((rc = copy(o, chain))) return rc;
         }

@@ -30,7 +30,8 @@ __global__ void amax_fold_kernel(unsigned *amax, int n) {
 // wave, each lane W consecutive channels per chunk (16-byte loads), so a
 // lane stores its W codes at once.
 template <int VPT, int RPW>
-__global__ __launch_bounds__(256) void ln8_kernel(const float *__restrict__ x, const float *__restrict__ gamma,
+__global__ __launch_bounds__(256) void ln8_kernel(float *x, float *const *xs, unsigned T, UDiv dT,
+                                                  const float *__restrict__ gamma,
                                                   const float *__restrict__ beta, int M, float eps,
                                                   const float *__restrict__ amax, unsigned char *__restrict__ out) {
     constexpr int C = VPT * 64;
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256) void ln8_kernel(const float *__restrict__ x, c
     float v[RPW][VPT];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
-        const float *xr = x + (size_t)min(row0 + r, M - 1) * C;
+        const float *xr = state_row(x, xs, T, dT, (unsigned)min(row0 + r, M - 1), C);
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
             const int base = (j * 64 + lane) * W;
@@ -124,18 +125,20 @@ __global__ void zero_u32_kernel(unsigned *p, size_t n) {
 }
 
 template <int VPT>
-hipError_t ln_fp8_static(const float *x, const float *g, const float *b, int M, float eps, const float *amax,
+hipError_t ln_fp8_static(const StateRows &x, const float *g, const float *b, int M, float eps, const float *amax,
                          unsigned char *out, hipStream_t s) {
     constexpr int RPW = 2;
-    ln8_kernel<VPT, RPW><<<(M + 4 * RPW - 1) / (4 * RPW), 256, 0, s>>>(x, g, b, M, eps, amax, out);
+    ln8_kernel<VPT, RPW><<<(M + 4 * RPW - 1) / (4 * RPW), 256, 0, s>>>(x.x, x.xs, x.T, udiv_make(x.T), g, b, M, eps,
+                                                                      amax, out);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_layernorm_fp8_static(const float *x, const float *gamma, const float *beta, int M, int C,
+hipError_t launch_layernorm_fp8_static(const StateRows &x, const float *gamma, const float *beta, int M, int C,
                                        float eps, const float *amax, unsigned char *out, hipStream_t stream) {
     if (M <= 0) return hipSuccess;
+    if (x.xs && x.T == 0) return hipErrorInvalidValue;
     switch (C) {
     case 128: return ln_fp8_static<2>(x, gamma, beta, M, eps, amax, out, stream);
     case 256: return ln_fp8_static<4>(x, gamma, beta, M, eps, amax, out, stream);

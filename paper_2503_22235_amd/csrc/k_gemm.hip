@@ -56,7 +56,7 @@ __device__ __forceinline__ void epilogue4(const EpiArgs &ep, int M, int N, int m
         v[0] = gelu_as(v[0]); v[1] = gelu_as(v[1]); v[2] = gelu_as(v[2]); v[3] = gelu_as(v[3]);
         store4((TO *)ep.out + (size_t)m * N + n, v);
     } else if constexpr (EPI == EPI_RESID) {
-        float *r = ep.resid + (size_t)m * N + n;
+        float *r = state_row(ep.resid, ep.resid_ptrs, (unsigned)ep.T, ep.dT, (unsigned)m, N) + n;
         float4 x = *(const float4 *)r;
         x.x += v[0]; x.y += v[1]; x.z += v[2]; x.w += v[3];
         *(float4 *)r = x;

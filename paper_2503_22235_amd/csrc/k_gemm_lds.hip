@@ -92,7 +92,8 @@ __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int
         }
     } else if constexpr (EPI == EPI_RESID) {
         // rr: the residual values at (m, n..n+3), loaded by the caller
-        *(float4 *)(ep.resid + (size_t)m * N + n) = make_float4(rr.x + v[0], rr.y + v[1], rr.z + v[2], rr.w + v[3]);
+        *(float4 *)(state_row(ep.resid, ep.resid_ptrs, (unsigned)ep.T, ep.dT, (unsigned)m, N) + n) =
+            make_float4(rr.x + v[0], rr.y + v[1], rr.z + v[2], rr.w + v[3]);
     } else {
         store4((bf16 *)ep.out + (size_t)m * N + n, v);
     }
@@ -146,7 +147,7 @@ __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, in
             store8((bf16 *)ep.out + (size_t)mg * N + n, v);
         }
     } else if constexpr (EPI == EPI_RESID) {
-        float4 *r = (float4 *)(ep.resid + (size_t)mg * N + n);
+        float4 *r = (float4 *)(state_row(ep.resid, ep.resid_ptrs, (unsigned)ep.T, ep.dT, (unsigned)mg, N) + n);
         float4 x0 = r[0], x1 = r[1];
         x0.x += v[0]; x0.y += v[1]; x0.z += v[2]; x0.w += v[3];
         x1.x += v[4]; x1.y += v[5]; x1.z += v[6]; x1.w += v[7];
@@ -552,7 +553,8 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
 #pragma unroll
                         for (int ii = i; ii < i + RI; ++ii) {
                             const int m = min(mt + wm * WM + 16 * ii + r16, M - 1);
-                            const float *r = ep.resid + (size_t)(m + ep.row0) * N + n0 + wn * WN + 16 * j + 4 * g;
+                            const float *r = state_row(ep.resid, ep.resid_ptrs, (unsigned)ep.T, ep.dT,
+                                                       (unsigned)(m + ep.row0), N) + n0 + wn * WN + 16 * j + 4 * g;
                             rz[ii][0] = *(const float4 *)r;
                             rz[ii][1] = *(const float4 *)(r + 16);
                         }

@@ -9,8 +9,10 @@ namespace {
 // every load instruction covers one contiguous span of a row; all rows'
 // loads are issued before any arithmetic.  Statistics are float32 with a
 // two-pass (mean, then centred squares) variance kept in registers.
+// Input rows come from one buffer x or from per-state buffers xs
+// (StateRows).
 template <int VPT, bool OBF, int RPW>
-__global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict__ x,
+__global__ __launch_bounds__(256) void layernorm_kernel(float *x, float *const *xs, unsigned T, UDiv dT,
                                                         const float *__restrict__ gamma,
                                                         const float *__restrict__ beta,
                                                         void *__restrict__ out, int M, float eps) {
@@ -23,7 +25,7 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict_
     float v[RPW][VPT];
 #pragma unroll
     for (int r = 0; r < RPW; ++r) {
-        const float *xr = x + (size_t)min(row0 + r, M - 1) * C;
+        const float *xr = state_row(x, xs, T, dT, (unsigned)min(row0 + r, M - 1), C);
 #pragma unroll
         for (int j = 0; j < NV; ++j) {
             const int base = (j * 64 + lane) * W;
@@ -80,13 +82,19 @@ __global__ __launch_bounds__(256) void layernorm_kernel(const float *__restrict_
 }
 
 template <int VPT>
-hipError_t ln_launch(const float *x, const float *g, const float *b, void *out, bool obf, int M, float eps,
+hipError_t ln_launch(const StateRows &x, const float *g, const float *b, void *out, bool obf, int M, float eps,
                      hipStream_t s) {
     constexpr int RPW = 2;
     const int grid = (M + 4 * RPW - 1) / (4 * RPW);
-    if (obf) layernorm_kernel<VPT, true, RPW><<<grid, 256, 0, s>>>(x, g, b, out, M, eps);
-    else layernorm_kernel<VPT, false, RPW><<<grid, 256, 0, s>>>(x, g, b, out, M, eps);
+    const UDiv dT = udiv_make(x.T);
+    if (obf) layernorm_kernel<VPT, true, RPW><<<grid, 256, 0, s>>>(x.x, x.xs, x.T, dT, g, b, out, M, eps);
+    else layernorm_kernel<VPT, false, RPW><<<grid, 256, 0, s>>>(x.x, x.xs, x.T, dT, g, b, out, M, eps);
     return hipGetLastError();
+}
+
+__global__ void set_ptrs_kernel(float **dst, PtrList ptrs, int n) {
+    const int i = threadIdx.x;
+    if (i < n) dst[i] = ptrs.p[i];
 }
 
 __global__ void nat_indices_kernel(int Z, int Y, int X, int Kz, int Ky, int Kx, unsigned periodic,
@@ -147,9 +155,10 @@ hipError_t launch_convert(const void *src, bool src_bf16, void *dst, bool dst_bf
     return hipGetLastError();
 }
 
-hipError_t launch_layernorm(const float *x, const float *gamma, const float *beta, void *out, bool out_bf16,
+hipError_t launch_layernorm(const StateRows &x, const float *gamma, const float *beta, void *out, bool out_bf16,
                             int M, int C, float eps, hipStream_t stream) {
     if (M <= 0) return hipSuccess;
+    if (x.xs && x.T == 0) return hipErrorInvalidValue;
     switch (C) {
     case 128: return ln_launch<2>(x, gamma, beta, out, out_bf16, M, eps, stream);
     case 256: return ln_launch<4>(x, gamma, beta, out, out_bf16, M, eps, stream);
@@ -157,6 +166,13 @@ hipError_t launch_layernorm(const float *x, const float *gamma, const float *bet
     case 1024: return ln_launch<16>(x, gamma, beta, out, out_bf16, M, eps, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_set_ptrs(float **dst, const PtrList &ptrs, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    if (n > 64) return hipErrorInvalidValue;
+    set_ptrs_kernel<<<1, 64, 0, stream>>>(dst, ptrs, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_nat_indices(int Z, int Y, int X, int Kz, int Ky, int Kx, unsigned periodic, int *out,

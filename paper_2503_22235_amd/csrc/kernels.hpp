@@ -8,10 +8,19 @@
 
 namespace wm {
 
+// Rows of the float32 residual stream [B*T][C]: one buffer x, or (xs set)
+// a device array of B state pointers, row m at xs[m / T] + (m % T) * C (the
+// states of a batch in separate buffers, e.g. serving slots).
+struct StateRows {
+    float *x;
+    float *const *xs;
+    unsigned T;
+};
+
 // --- LayerNorm over the channel axis, float32 statistics -----------------
 // out[m][c] = (x[m][c] - mu_m) / sqrt(var_m + eps) * gamma[c] + beta[c]
 // with biased variance; out element type is float or bf16.
-hipError_t launch_layernorm(const float *x, const float *gamma, const float *beta,
+hipError_t launch_layernorm(const StateRows &x, const float *gamma, const float *beta,
                             void *out, bool out_bf16, int M, int C, float eps,
                             hipStream_t stream);
 
@@ -38,10 +47,19 @@ inline UDiv udiv_make(unsigned d) {
     return UDiv{(unsigned)((1ull << (31 + l)) / d + 1), l - 1};
 }
 __device__ __forceinline__ unsigned udiv(unsigned n, UDiv d) { return d.s < 0 ? n : (__umulhi(n, d.m) >> d.s); }
+// Row m (< 2^31) of the residual stream of StateRows x with n columns.
+__device__ __forceinline__ float *state_row(float *x, float *const *xs, unsigned T, UDiv dT, unsigned m, int n) {
+    if (!xs) return x + (size_t)m * n;
+    const unsigned b = udiv(m, dT);
+    return xs[b] + (size_t)(m - b * T) * n;
+}
 struct EpiArgs {
     const float *bias;  // [N]
     void *out;          // EPI_QKV / EPI_GELU / EPI_STORE output
     float *resid;       // EPI_RESID target
+    // EPI_RESID on states in separate buffers: row m of the target is
+    // resid_ptrs[m / T] + (m % T) * N (T and dT set; resid unused)
+    float *const *resid_ptrs;
     int C, H;           // EPI_QKV: model width and heads (d = 32)
     int part0;          // EPI_QKV: part (0 Q, 1 K, 2 V) of output column 0
     float qscale;       // EPI_QKV: factor on Q columns
@@ -132,12 +150,18 @@ constexpr int AMAX_STRIDE = 512;            // slots per copy (>= 8 per state x 
 // atomicMax into amax[shard*AMAX_STRIDE + b*amax_stride] (fold afterwards)
 hipError_t launch_amax_bf16(const void *x, size_t per_state, int B, unsigned *amax, int amax_stride,
                             hipStream_t stream);
+// dst[i] = ptrs[i] for i < n (n <= 64): a batch's state pointers written by
+// a kernel, in stream order, with no host buffer to keep alive
+struct PtrList {
+    float *p[64];
+};
+hipError_t launch_set_ptrs(float **dst, const PtrList &ptrs, int n, hipStream_t stream);
 // zero n 32-bit words (a kernel, so graph capture records no memset node)
 hipError_t launch_zero_u32(unsigned *p, size_t n, hipStream_t stream);
 hipError_t launch_amax_fold(unsigned *amax, int n, hipStream_t stream);
 // LayerNorm + quantize with one static amax (device float at `amax`) for
 // every row: a single pass.
-hipError_t launch_layernorm_fp8_static(const float *x, const float *gamma, const float *beta, int M, int C,
+hipError_t launch_layernorm_fp8_static(const StateRows &x, const float *gamma, const float *beta, int M, int C,
                                        float eps, const float *amax, unsigned char *out, hipStream_t stream);
 // float32 -> e4m3 codes = RNE(clamp(x * mul, +-448))
 hipError_t launch_quant_f32(const float *in, size_t n, float mul, unsigned char *out, hipStream_t stream);

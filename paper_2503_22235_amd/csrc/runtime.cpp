@@ -80,10 +80,11 @@ int prof_end(wm_ctx *ctx, hipStream_t s) {
 //   written head-major); o = NA(q, k, v); x += o W_o + b_o;
 //   w = LN2(x); h = GELU(w W_1 + b_1); x += h W_2 + b_2.
 // u, o and w share one buffer; qkv and h share the other.
-static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s);
+static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, float *const *xs,
+                         hipStream_t s);
 
-int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s) {
-    if (p->prec == WM_FP8_E4M3) return run_block_fp8(ctx, p, block, B, x, s);
+int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, float *const *xs, hipStream_t s) {
+    if (p->prec == WM_FP8_E4M3) return run_block_fp8(ctx, p, block, B, x, xs, s);
     const wm_grid &g = p->g;
     const BlockWeights &w = p->blk[block];
     const long T = (long)g.Z * g.Y * g.X;
@@ -128,7 +129,8 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     if ((rc = prof_begin(ctx, s, kind)) != WM_OK) return rc;        \
     if ((e = (call)) != hipSuccess) return hip_fail(e, what);       \
     if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
-    WM_TIMED(PK_LN1, launch_layernorm(x, w.ln1_g, w.ln1_b, act, bf, M, C, 1e-5f, s), "LN1")
+    const StateRows xr{x, xs, (unsigned)T};
+    WM_TIMED(PK_LN1, launch_layernorm(xr, w.ln1_g, w.ln1_b, act, bf, M, C, 1e-5f, s), "LN1")
     EpiArgs ep{};
     ep.bias = w.b_qkv;
     ep.out = big;
@@ -176,8 +178,11 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     EpiArgs er{};
     er.bias = w.b_o;
     er.resid = x;
+    er.resid_ptrs = xs;
+    er.T = T;
+    er.dT = udiv_make((unsigned)T);
     WM_TIMED(PK_PROJ, launch_gemm(act, w.w_o, M, C, C, bf, EPI_RESID, er, s), "proj")
-    WM_TIMED(PK_LN2, launch_layernorm(x, w.ln2_g, w.ln2_b, act, bf, M, C, 1e-5f, s), "LN2")
+    WM_TIMED(PK_LN2, launch_layernorm(xr, w.ln2_g, w.ln2_b, act, bf, M, C, 1e-5f, s), "LN2")
     EpiArgs eg{};
     eg.bias = w.b_1;
     eg.out = big;
@@ -186,12 +191,14 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
     EpiArgs e2{};
     e2.bias = w.b_2;
     e2.resid = x;
+    e2.resid_ptrs = xs;
+    e2.T = T;
+    e2.dT = udiv_make((unsigned)T);
     WM_TIMED(PK_MLP2, launch_gemm(big, w.w_2, M, C, F, bf, EPI_RESID, e2, s), "MLP2")
 #undef WM_TIMED
     return WM_OK;
 }
 
-// FP8 block: LayerNorms quantize their outputs per state (two passes), the
 // Every GEMM and both attention contractions run on e4m3 operands with
 // static per-tensor scales fixed at processor creation from the weights
 // (BlockWeights): each producer stores e4m3 codes directly -- the
@@ -200,7 +207,8 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hi
 // output) -- and each consumer dequantizes its MFMA sums with the product
 // of the two scales.  Softmax, LayerNorm statistics and the residual stream
 // stay float32.
-static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s) {
+static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, float *const *xs,
+                         hipStream_t s) {
     const wm_grid &g = p->g;
     const BlockWeights &w = p->blk[block];
     const long T = (long)g.Z * g.Y * g.X;
@@ -221,7 +229,8 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     if ((rc = prof_end(ctx, s)) != WM_OK) return rc;
     if (B > 64) return fail(WM_EINVAL, "FP8 processors take at most 64 states per call");
     if (!fp8_ring_applies(&g, B, 32)) return fail(WM_EINVAL, "no e4m3 attention kernel for this grid and batch");
-    WM_TIMED(PK_LN1, launch_layernorm_fp8_static(x, w.ln1_g, w.ln1_b, M, C, 1e-5f, w.ln1_amax, act8, s), "LN1")
+    const StateRows xr{x, xs, (unsigned)T};
+    WM_TIMED(PK_LN1, launch_layernorm_fp8_static(xr, w.ln1_g, w.ln1_b, M, C, 1e-5f, w.ln1_amax, act8, s), "LN1")
     EpiArgs ep{};
     ep.bias = w.b_qkv;
     ep.out = q8;
@@ -270,11 +279,14 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     EpiArgs er{};
     er.bias = w.b_o;
     er.resid = x;
+    er.resid_ptrs = xs;
+    er.T = T;
+    er.dT = udiv_make((unsigned)T);
     er.a_dequant = w.qkv_amax_h[2] / 448.0f;   // o is coded at v's scale
     er.w_dequant = w.dq_o;
     er.T = T;
     WM_TIMED(PK_PROJ, launch_gemm_fp8(o8, w.w_o, M, C, C, EPI_RESID, er, s), "proj")
-    WM_TIMED(PK_LN2, launch_layernorm_fp8_static(x, w.ln2_g, w.ln2_b, M, C, 1e-5f, w.ln2_amax, act8, s), "LN2")
+    WM_TIMED(PK_LN2, launch_layernorm_fp8_static(xr, w.ln2_g, w.ln2_b, M, C, 1e-5f, w.ln2_amax, act8, s), "LN2")
     EpiArgs eg{};
     eg.bias = w.b_1;
     eg.out = h8;
@@ -288,6 +300,9 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     EpiArgs e2{};
     e2.bias = w.b_2;
     e2.resid = x;
+    e2.resid_ptrs = xs;
+    e2.T = T;
+    e2.dT = udiv_make((unsigned)T);
     e2.a_dequant = w.h_amax_h / 448.0f;
     e2.w_dequant = w.dq_2;
     e2.T = T;
@@ -296,9 +311,9 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     return WM_OK;
 }
 
-int run_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, hipStream_t s) {
+int run_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, float *const *xs, hipStream_t s) {
     for (int b = 0; b < p->nb; ++b) {
-        int rc = run_block(ctx, p, b, B, x, s);
+        int rc = run_block(ctx, p, b, B, x, xs, s);
         if (rc) return rc;
     }
     return WM_OK;

@@ -103,8 +103,11 @@ int reserve_block_workspace(wm_ctx *ctx, const wm_processor *p, int B);
 int prof_begin(wm_ctx *ctx, hipStream_t s, int kind);
 int prof_end(wm_ctx *ctx, hipStream_t s);
 // Enqueue one block / one step on `s` (workspace already reserved).
-int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, hipStream_t s);
-int run_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, hipStream_t s);
+// x: the float32 residual stream [B*T][C] in one buffer, or (xs set, x
+// unused) B states in separate buffers whose pointers are in the device
+// array xs.
+int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, float *const *xs, hipStream_t s);
+int run_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, float *const *xs, hipStream_t s);
 // Host OCP e4m3 encoding, round to nearest even, saturating at +-448.
 unsigned char host_fp8_e4m3(float x);
 

@@ -10,9 +10,12 @@
 //   3. if fewer than two step batches are queued on the compute stream,
 //      forms the next batch: the admitted, idle requests whose next
 //      processor (greedy 6 h / 1 h schedule) matches that of the oldest such
-//      request, up to max_batch of them, gathers their slots into the batch
-//      buffer, enqueues one processor step over the batch and scatters the
-//      states back.
+//      request, up to max_batch of them, and enqueues one processor step
+//      over the batch: with float32 slots the kernels read and write the
+//      slots in place through a device array of the batch's slot pointers
+//      (written by a small kernel on the compute stream, so no host buffer
+//      has to outlive the call); with bfloat16 slots (half the memory) the
+//      slots are converted into a float32 batch buffer and back.
 // Requests join and leave between steps.  Kernels compute each state's
 // tokens the same way whatever the batch, so results match a run alone.
 #include <hip/hip_runtime.h>
@@ -72,7 +75,8 @@ struct wm_server {
     void *slot_mem = nullptr;
     int nslots = 0;
     std::vector<int> free_slots;
-    float *batch = nullptr;               // [max_batch][elems] float32
+    float *batch = nullptr;               // [max_batch][elems] float32 (bf16 slots)
+    float **dptrs = nullptr;              // device array of the batch's slot pointers (f32 slots)
     float *stage_in = nullptr, *stage_out = nullptr;   // float32 staging (bf16 slots)
     float *pin_in = nullptr, *pin_out = nullptr;       // pinned host staging of one state
     hipStream_t s_comp = nullptr, s_copy = nullptr;
@@ -240,25 +244,33 @@ struct wm_server {
                     if (r->sched[r->cursor] == size) b.reqs.push_back(r);
                 }
                 const int B = (int)b.reqs.size();
-                for (int i = 0; i < B; ++i) {
-                    float *dst = batch + (size_t)i * elems;
-                    void *src = slot_ptr(b.reqs[i]->slot);
-                    e = cfg.state_bf16 ? launch_convert(src, true, dst, false, elems, s_comp)
-                                       : hipMemcpyAsync(dst, src, elems * 4, hipMemcpyDeviceToDevice, s_comp);
-                    if (e != hipSuccess) return set_error(WM_EHIP, "gather", e), true;
+                const wm_processor *proc = size == 6 ? p6 : p1;
+                int rc;
+                if (!cfg.state_bf16) {
+                    // in place: the step's kernels address the slots through dptrs
+                    // (the previous batch's step precedes this write on s_comp)
+                    PtrList pl{};
+                    for (int i = 0; i < B; ++i) pl.p[i] = (float *)slot_ptr(b.reqs[i]->slot);
+                    if ((e = launch_set_ptrs(dptrs, pl, B, s_comp)) != hipSuccess)
+                        return set_error(WM_EHIP, "slot pointers", e), true;
+                    rc = run_step(ctx, proc, B, nullptr, dptrs, s_comp);
+                } else {
+                    for (int i = 0; i < B; ++i) {
+                        e = launch_convert(slot_ptr(b.reqs[i]->slot), true, batch + (size_t)i * elems, false, elems,
+                                           s_comp);
+                        if (e != hipSuccess) return set_error(WM_EHIP, "gather", e), true;
+                    }
+                    rc = run_step(ctx, proc, B, batch, nullptr, s_comp);
+                    for (int i = 0; rc == WM_OK && i < B; ++i) {
+                        e = launch_convert(batch + (size_t)i * elems, false, slot_ptr(b.reqs[i]->slot), true, elems,
+                                           s_comp);
+                        if (e != hipSuccess) return set_error(WM_EHIP, "scatter", e), true;
+                    }
                 }
-                const int rc = run_step(ctx, size == 6 ? p6 : p1, B, batch, s_comp);
                 if (rc != WM_OK) {
                     err_code = rc;
                     snprintf(err_msg, sizeof err_msg, "step: %s", wm_last_error());
                     return true;
-                }
-                for (int i = 0; i < B; ++i) {
-                    const float *src = batch + (size_t)i * elems;
-                    void *dst = slot_ptr(b.reqs[i]->slot);
-                    e = cfg.state_bf16 ? launch_convert(src, false, dst, true, elems, s_comp)
-                                       : hipMemcpyAsync(dst, src, elems * 4, hipMemcpyDeviceToDevice, s_comp);
-                    if (e != hipSuccess) return set_error(WM_EHIP, "scatter", e), true;
                 }
                 b.ev = get_event();
                 if (!b.ev || (e = hipEventRecord(b.ev, s_comp)) != hipSuccess)
@@ -323,9 +335,14 @@ int wm_serve_create(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
     if (rc) return cleanup(rc);
     rc = reserve_block_workspace(s->ctx, p1, cfg->max_batch);
     if (rc) return cleanup(rc);
-    if ((e = hipMalloc(&s->batch, (size_t)cfg->max_batch * s->elems * 4)) != hipSuccess) {
+    if (cfg->state_bf16) {
+        if ((e = hipMalloc(&s->batch, (size_t)cfg->max_batch * s->elems * 4)) != hipSuccess) {
+            (void)hipGetLastError();
+            return cleanup(fail(WM_ENOMEM, "batch buffer: %s", hipGetErrorString(e)));
+        }
+    } else if ((e = hipMalloc(&s->dptrs, 64 * sizeof(float *))) != hipSuccess) {
         (void)hipGetLastError();
-        return cleanup(fail(WM_ENOMEM, "batch buffer: %s", hipGetErrorString(e)));
+        return cleanup(fail(WM_ENOMEM, "slot pointer array: %s", hipGetErrorString(e)));
     }
     if ((e = hipHostMalloc((void **)&s->pin_in, s->elems * 4, hipHostMallocDefault)) != hipSuccess ||
         (e = hipHostMalloc((void **)&s->pin_out, s->elems * 4, hipHostMallocDefault)) != hipSuccess) {
@@ -450,6 +467,7 @@ void wm_serve_destroy(wm_server *s) {
     if (s->s_copy) (void)hipStreamDestroy(s->s_copy);
     if (s->slot_mem) (void)hipFree(s->slot_mem);
     if (s->batch) (void)hipFree(s->batch);
+    if (s->dptrs) (void)hipFree(s->dptrs);
     if (s->stage_in) (void)hipFree(s->stage_in);
     if (s->stage_out) (void)hipFree(s->stage_out);
     if (s->pin_in) (void)hipHostFree(s->pin_in);

@@ -277,6 +277,35 @@ def test_step_small_config_and_batch_invariance(env, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("grid", ["odd", "cfg1"])
+def test_step_states_in_separate_buffers(env, prec, grid):
+    """wm_processor_step_states: B states in separate allocations, handed
+    over in a scrambled order through a device array of pointers, give bit
+    for bit what wm_processor_step gives the same states stacked in one
+    buffer (the kernels address the residual rows through the pointers)."""
+    wm, torch, ctx = env
+    if grid == "odd":   # T = 405: rows of a GEMM tile and a LayerNorm row pair straddle states
+        g, B, nb = S.Grid(Z=3, Y=9, X=15, C=128, heads=4, Kz=3, Ky=5, Kx=5), 3, 2
+    else:
+        g, B, nb = S.CFG1, 2, 2
+    params = S.processor_params(g, nb, 1)
+    x = S.latent_state(g, B, 6)
+    say(f"step on separate state buffers {grid} prec {prec}")
+    p = wm.wm_processor_create(ctx, g, nb, 4, prec, params)
+    xb = torch.from_numpy(x).cuda()
+    wm.wm_processor_step(ctx, p, B, xb)
+    order = list(range(B))[::-1]
+    bufs = {b: torch.from_numpy(x[b:b + 1].copy()).cuda() for b in range(B)}
+    ptrs = torch.tensor([bufs[b].data_ptr() for b in order], dtype=torch.int64, device="cuda")
+    wm.wm_processor_step_states(ctx, p, B, ptrs)
+    for b in range(B):
+        assert torch.equal(bufs[b], xb[b:b + 1]), f"state {b} differs from the stacked step"
+    with pytest.raises(wm.WmError):
+        wm.wm_processor_step_states(ctx, p, 65, ptrs)
+    p.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_block_batch_invariance_odd_token_count(env, prec):
     """T = 3 x 9 x 15 = 405 tokens (odd): rows of the second and third states
     land at other positions within GEMM tiles and LayerNorm row pairs than
