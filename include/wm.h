@@ -281,7 +281,12 @@ int wm_rollout(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
  * on the slots in place (the kernels address the batch's states through a
  * device array of slot pointers, as wm_processor_step_states); with
  * bfloat16 slots (half the memory per request) each step converts the
- * batch's slots into a float32 buffer and back.  Finished states are copied out
+ * batch's slots into a float32 buffer and back.  Every step's kernels read
+ * fixed addresses (the pointer array or the batch buffer and the server's
+ * own workspace), so with cfg.graphs the step of a (processor, batch size)
+ * is captured once into a HIP graph and replayed for every later batch of
+ * that shape; only the pointer array (or the conversions) changes between
+ * replays.  Finished states are copied out
  * on the copy stream.  Each request's result does not depend on what it
  * was batched with (every kernel computes a state's tokens the same way
  * whatever the batch).  Calls are thread-safe. */
@@ -290,6 +295,9 @@ typedef struct {
     int state_bf16;            /* 1: slots hold bfloat16 states between steps      */
     size_t hbm_budget_bytes;   /* slot memory cap; 0 = 3/4 of the free HBM         */
     int max_slots;             /* 0 = as many as the budget allows (<= 1024)        */
+    int graphs;                /* 1: each step after the first of its (processor,
+                                  batch size) replays a HIP graph captured from
+                                  that step's launches (one graph launch per step) */
 } wm_serve_cfg;
 
 typedef struct {
@@ -301,8 +309,9 @@ typedef struct {
     int max_cobatch;           /* most requests in one step launch it was part of  */
 } wm_req_stats;
 
-/* p6, p1 must share one grid and stay alive until wm_serve_destroy.  The
- * server takes its own streams and workspace on ctx's device. */
+/* p6, p1 must share one grid and stay alive, with their rotary setting
+ * unchanged, until wm_serve_destroy.  The server takes its own streams and
+ * workspace on ctx's device. */
 int wm_serve_create(wm_ctx *ctx, const wm_processor *p6, const wm_processor *p1,
                     const wm_serve_cfg *cfg, wm_server **out);
 /* Queue a forecast of lead_hours >= 0 from HOST float32 x0 [Z][Y][X][C];

@@ -37,7 +37,7 @@ class WmError(RuntimeError):
 
 class wm_serve_cfg(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int), ("state_bf16", ctypes.c_int),
-                ("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int)]
+                ("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int), ("graphs", ctypes.c_int)]
 
 
 class wm_req_stats(ctypes.Structure):
@@ -332,8 +332,8 @@ class Server:
             pass
 
 
-def wm_serve_create(ctx, p6, p1, max_batch=8, state_bf16=True, hbm_budget_bytes=0, max_slots=0):
-    cfg = wm_serve_cfg(max_batch, 1 if state_bf16 else 0, hbm_budget_bytes, max_slots)
+def wm_serve_create(ctx, p6, p1, max_batch=8, state_bf16=True, hbm_budget_bytes=0, max_slots=0, graphs=False):
+    cfg = wm_serve_cfg(max_batch, 1 if state_bf16 else 0, hbm_budget_bytes, max_slots, 1 if graphs else 0)
     h = _vp()
     _check(lib().wm_serve_create(ctx.handle, p6.handle, p1.handle, ctypes.byref(cfg), ctypes.byref(h)))
     g = p6.grid

@@ -26,7 +26,9 @@
 #include <cstring>
 #include <deque>
 #include <exception>
+#include <map>
 #include <mutex>
+#include <set>
 #include <new>
 #include <thread>
 #include <unordered_map>
@@ -77,6 +79,11 @@ struct wm_server {
     std::vector<int> free_slots;
     float *batch = nullptr;               // [max_batch][elems] float32 (bf16 slots)
     float **dptrs = nullptr;              // device array of the batch's slot pointers (f32 slots)
+    // cfg.graphs: the step of (processor step size, batch size) as a graph,
+    // captured the second time that shape runs (the first, eager, run sets
+    // the kernels' one-time attributes outside any capture)
+    std::set<std::pair<int, int>> warmed;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     float *stage_in = nullptr, *stage_out = nullptr;   // float32 staging (bf16 slots)
     float *pin_in = nullptr, *pin_out = nullptr;       // pinned host staging of one state
     hipStream_t s_comp = nullptr, s_copy = nullptr;
@@ -246,6 +253,36 @@ struct wm_server {
                 const int B = (int)b.reqs.size();
                 const wm_processor *proc = size == 6 ? p6 : p1;
                 int rc;
+                // the step itself: eager, or the graph of its shape
+                auto step = [&]() -> int {
+                    float *x = cfg.state_bf16 ? batch : nullptr;
+                    float *const *xs = cfg.state_bf16 ? nullptr : dptrs;
+                    const std::pair<int, int> key{size, B};
+                    if (!cfg.graphs || !warmed.count(key)) {
+                        warmed.insert(key);
+                        return run_step(ctx, proc, B, x, xs, s_comp);
+                    }
+                    auto it = graphs.find(key);
+                    if (it == graphs.end()) {
+                        hipGraph_t gr = nullptr;
+                        hipGraphExec_t ex = nullptr;
+                        if ((e = hipStreamBeginCapture(s_comp, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+                            return hip_fail(e, "hipStreamBeginCapture");
+                        const int rs = run_step(ctx, proc, B, x, xs, s_comp);
+                        const hipError_t ee = hipStreamEndCapture(s_comp, &gr);
+                        if (rs != WM_OK) {
+                            if (gr) (void)hipGraphDestroy(gr);
+                            return rs;
+                        }
+                        if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+                        e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                        (void)hipGraphDestroy(gr);
+                        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+                        it = graphs.emplace(key, ex).first;
+                    }
+                    e = hipGraphLaunch(it->second, s_comp);
+                    return e == hipSuccess ? WM_OK : hip_fail(e, "hipGraphLaunch");
+                };
                 if (!cfg.state_bf16) {
                     // in place: the step's kernels address the slots through dptrs
                     // (the previous batch's step precedes this write on s_comp)
@@ -253,14 +290,14 @@ struct wm_server {
                     for (int i = 0; i < B; ++i) pl.p[i] = (float *)slot_ptr(b.reqs[i]->slot);
                     if ((e = launch_set_ptrs(dptrs, pl, B, s_comp)) != hipSuccess)
                         return set_error(WM_EHIP, "slot pointers", e), true;
-                    rc = run_step(ctx, proc, B, nullptr, dptrs, s_comp);
+                    rc = step();
                 } else {
                     for (int i = 0; i < B; ++i) {
                         e = launch_convert(slot_ptr(b.reqs[i]->slot), true, batch + (size_t)i * elems, false, elems,
                                            s_comp);
                         if (e != hipSuccess) return set_error(WM_EHIP, "gather", e), true;
                     }
-                    rc = run_step(ctx, proc, B, batch, nullptr, s_comp);
+                    rc = step();
                     for (int i = 0; rc == WM_OK && i < B; ++i) {
                         e = launch_convert(batch + (size_t)i * elems, false, slot_ptr(b.reqs[i]->slot), true, elems,
                                            s_comp);
@@ -466,6 +503,7 @@ void wm_serve_destroy(wm_server *s) {
     if (s->s_comp) (void)hipStreamDestroy(s->s_comp);
     if (s->s_copy) (void)hipStreamDestroy(s->s_copy);
     if (s->slot_mem) (void)hipFree(s->slot_mem);
+    for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
     if (s->batch) (void)hipFree(s->batch);
     if (s->dptrs) (void)hipFree(s->dptrs);
     if (s->stage_in) (void)hipFree(s->stage_in);

@@ -86,6 +86,40 @@ def test_serve_alone_equals_mix(env, prec, bf16_state):
     p1.close()
 
 
+@pytest.mark.parametrize("prec,bf16_state", [(1, False), (2, False), (1, True)])
+def test_serve_graph_replays_equal_eager(env, prec, bf16_state):
+    """cfg.graphs: each (processor, batch size) step runs eagerly once, is
+    then captured into a HIP graph and replayed for every later batch of that
+    shape, with the server's own eager work (pointer writes or conversions,
+    copies, event polls) between replays.  Every result must equal the
+    server without graphs bit for bit, and (float32 slots) a direct rollout."""
+    wm, torch, ctx, g, p6p, p1p = env
+    p6 = wm.wm_processor_create(ctx, g, 2, 4, prec, p6p)
+    p1 = wm.wm_processor_create(ctx, g, 2, 4, prec, p1p)
+    shape = (g.Z, g.Y, g.X, g.C)
+    rng = np.random.default_rng(5)
+    leads = [int(v) for v in rng.integers(1, 40, size=12)]
+    states = S.latent_state(g, len(leads), seed=2)
+    res = {}
+    for graphs in (False, True):
+        say("serve graphs", graphs, prec, bf16_state, leads)
+        srv = wm.wm_serve_create(ctx, p6, p1, max_batch=3, state_bf16=bf16_state, max_slots=5, graphs=graphs)
+        ids = [wm.wm_serve_submit(srv, states[i], leads[i]) for i in range(len(leads))]
+        out, st = drain(wm, srv, ids, shape)
+        srv.close()
+        res[graphs] = [out[r] for r in ids]
+        assert sum(s["steps"] for s in st.values()) == sum(len(O.schedule(l)) for l in leads)
+    for i in range(len(leads)):
+        assert np.array_equal(res[True][i], res[False][i]), f"request {i}: graph replay differs from eager"
+    if not bf16_state:
+        for i in (0, 5, 11):
+            xd = torch.from_numpy(states[i:i + 1].copy()).cuda()
+            wm.wm_rollout(ctx, p6, p1, 1, xd, leads[i])
+            assert np.array_equal(xd.cpu().numpy()[0], res[True][i])
+    p6.close()
+    p1.close()
+
+
 def test_serve_result_against_oracle(env):
     wm, torch, ctx, g, p6p, p1p = env
     p6 = wm.wm_processor_create(ctx, g, 2, 4, 1, p6p)
