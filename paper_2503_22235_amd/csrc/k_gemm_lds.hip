@@ -83,7 +83,7 @@ __device__ __forceinline__ float epilogue4(const EpiArgs &ep, int N, long m, int
         if (ep.out8) *(unsigned *)((unsigned char *)ep.out + o) = e4m3x4(v[0], v[1], v[2], v[3]);
         else store4((bf16 *)ep.out + o, v);
     } else if constexpr (EPI == EPI_GELU) {
-        v[0] = gelu_as(v[0]); v[1] = gelu_as(v[1]); v[2] = gelu_as(v[2]); v[3] = gelu_as(v[3]);
+        v[0] = gelu_as4(v[0]); v[1] = gelu_as4(v[1]); v[2] = gelu_as4(v[2]); v[3] = gelu_as4(v[3]);
         if (ep.out8) {
             const float om = ep.out_mul[0];
             *(unsigned *)((unsigned char *)ep.out + (size_t)m * N + n) = e4m3x4(v[0] * om, v[1] * om, v[2] * om, v[3] * om);
@@ -138,7 +138,7 @@ __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, in
         else store8((bf16 *)ep.out + o, v);
     } else if constexpr (EPI == EPI_GELU) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = gelu_as(v[i]);
+        for (int i = 0; i < 8; ++i) v[i] = gelu_as4(v[i]);
         if (ep.out8) {
             const float om = ep.out_mul[0];
             *(uint2 *)((unsigned char *)ep.out + (size_t)mg * N + n) =
