@@ -84,6 +84,7 @@ struct wm_server {
     // the kernels' one-time attributes outside any capture)
     std::set<std::pair<int, int>> warmed;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::set<std::pair<int, int>> no_graph;   // shapes whose capture failed: they stay eager
     float *stage_in = nullptr, *stage_out = nullptr;   // float32 staging (bf16 slots)
     float *pin_in = nullptr, *pin_out = nullptr;       // pinned host staging of one state
     hipStream_t s_comp = nullptr, s_copy = nullptr;
@@ -258,26 +259,32 @@ struct wm_server {
                     float *x = cfg.state_bf16 ? batch : nullptr;
                     float *const *xs = cfg.state_bf16 ? nullptr : dptrs;
                     const std::pair<int, int> key{size, B};
-                    if (!cfg.graphs || !warmed.count(key)) {
+                    if (!cfg.graphs || !warmed.count(key) || no_graph.count(key)) {
                         warmed.insert(key);
                         return run_step(ctx, proc, B, x, xs, s_comp);
                     }
                     auto it = graphs.find(key);
                     if (it == graphs.end()) {
+                        // a shape whose capture fails runs eagerly from then on
+                        // (nothing recorded during a capture has executed)
+                        auto eager = [&]() {
+                            (void)hipGetLastError();
+                            no_graph.insert(key);
+                            return run_step(ctx, proc, B, x, xs, s_comp);
+                        };
                         hipGraph_t gr = nullptr;
                         hipGraphExec_t ex = nullptr;
-                        if ((e = hipStreamBeginCapture(s_comp, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-                            return hip_fail(e, "hipStreamBeginCapture");
+                        if (hipStreamBeginCapture(s_comp, hipStreamCaptureModeThreadLocal) != hipSuccess) return eager();
                         const int rs = run_step(ctx, proc, B, x, xs, s_comp);
                         const hipError_t ee = hipStreamEndCapture(s_comp, &gr);
                         if (rs != WM_OK) {
                             if (gr) (void)hipGraphDestroy(gr);
                             return rs;
                         }
-                        if (ee != hipSuccess) return hip_fail(ee, "hipStreamEndCapture");
+                        if (ee != hipSuccess) return eager();
                         e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
                         (void)hipGraphDestroy(gr);
-                        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+                        if (e != hipSuccess) return eager();
                         it = graphs.emplace(key, ex).first;
                     }
                     e = hipGraphLaunch(it->second, s_comp);
