@@ -596,22 +596,29 @@ def test_block_sharp_attention(env, gi):
         p.close()
 
 
-def test_block_width_1024_sampled(env):
-    """The encoder/decoder width: one BF16 block at 8 x 90 x 180 with
-    C=1024 (32 heads), window 5x7x7, sampled tokens."""
+@pytest.mark.parametrize("prec", [1, 2])
+def test_block_width_1024_sampled(env, prec):
+    """The encoder/decoder width: one block at 8 x 90 x 180 with C=1024
+    (32 heads), window 5x7x7, sampled tokens; BF16, and FP8 (its static
+    scales, the 4 QKV feature tiles per part and the V workgroups at this
+    width) held to the FP8 block bounds on the total and the increment."""
     wm, torch, ctx = env
     g = S.Grid(Z=8, Y=90, X=180, C=1024, heads=32, Kz=5, Ky=7, Kx=7, periodic_mask=4)
     params = S.processor_params(g, 1, 1)
     x = S.latent_state(g, 1, 0)
     r = np.random.default_rng(9)
     tok = np.unique(np.concatenate([r.choice(g.T, 200, replace=False), np.arange(0, g.X, 9)]))
-    p = wm.wm_processor_create(ctx, g, 1, 4, wm.WM_BF16, params)
+    p = wm.wm_processor_create(ctx, g, 1, 4, prec, params)
     y = torch.from_numpy(x).cuda()
-    say("block C=1024")
+    say(f"block C=1024 prec {prec}")
     wm.wm_processor_block(ctx, p, 0, 1, y)
     got = y.reshape(g.T, g.C)[torch.from_numpy(tok).cuda()].cpu().numpy()
     ref = O.block_at(x[0], S.split_block_params(g, params, 0), g, tok)
-    err = O.rel_l2(got, ref)
-    say(f"  rel_l2={err:.3e}")
-    assert err <= TOL[1]
+    xs = x[0].reshape(g.T, g.C)[tok]
+    err, inc = O.rel_l2(got, ref), O.rel_l2(got - xs, ref - xs)
+    say(f"  rel_l2={err:.3e} increment={inc:.3e}")
+    if prec == 1:
+        assert err <= TOL[1]
+    else:
+        assert err <= 1e-1 and inc <= 1e-1
     p.close()
