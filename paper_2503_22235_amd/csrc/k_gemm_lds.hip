@@ -188,6 +188,11 @@ __device__ __forceinline__ void wait_stages(int later) {
 // the tile's first, so its first k-step adds to zero instead of acc.
 // SWAP: the activation tile is the MFMA "A" operand, so a lane holds four
 // consecutive tokens of one output feature (the blocked V layout).
+// The bf16 MFMA block of each k-step runs at raised wave priority, so that a
+// wave with its operands in registers issues ahead of waves still loading
+// from LDS or in their epilogue (measured 1-3% faster on the bf16
+// projections; the e4m3 stage, whose weight loads sit between its MFMAs, was
+// no faster with it).
 template <bool FIRST, bool FP8, int TM, int TN, int KSTEPS, int BKB, bool SWAP = false>
 __device__ __forceinline__ void mma_stage(const unsigned char *sa, const unsigned char *sw, const int *aoff,
                                           const int *woff, f32x4 (&acc)[TN][TM]) {
@@ -225,6 +230,7 @@ __device__ __forceinline__ void mma_stage(const unsigned char *sa, const unsigne
             for (int i = 0; i < TM; ++i) af[i] = *(const bf16x8 *)(sa + aoff[ks] + 16 * i * BKB);
 #pragma unroll
             for (int j = 0; j < TN; ++j) wf[j] = *(const bf16x8 *)(sw + woff[ks] + 16 * j * BKB);
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -233,6 +239,7 @@ __device__ __forceinline__ void mma_stage(const unsigned char *sa, const unsigne
                                                                                0, 0, 0)
                                      : __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[j], af[i], FIRST && ks == 0 ? zero : acc[j][i],
                                                                                0, 0, 0);
+            __builtin_amdgcn_s_setprio(0);
         }
     }
 }
