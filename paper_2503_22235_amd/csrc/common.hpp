@@ -40,6 +40,16 @@ __device__ __forceinline__ float bf2f(bf16 b) {
     return bf_bits2f(__builtin_bit_cast(unsigned short, b));
 }
 
+// Sum over the 4 lanes l, l^16, l^32, l^48 (in the MFMA layouts, the lanes
+// that hold the same token or query); every one of them gets the same bits
+// (same operand order).
+__device__ __forceinline__ float xsum16_32(float v) {
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
 // Four floats -> four OCP e4m3 codes (byte i = value i), round to nearest
 // even, saturated at +-448 (the gfx950 conversion instruction rounds; the
 // clamp keeps out-of-range values finite).

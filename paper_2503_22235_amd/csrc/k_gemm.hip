@@ -225,7 +225,7 @@ hipError_t launch_gemm(const void *A, const void *W, int M, int N, int K, bool a
     if (M <= 0) return hipSuccess;
     if (a_bf16 && gemm_lds_applies(M, N, K)) return launch_gemm_lds(A, W, M, N, K, epi, ep, stream);
     // permuted W rows and the blocked V layout are the LDS kernels' only
-    if (ep.perm || ep.vt || ep.out8) return hipErrorInvalidValue;
+    if (ep.perm || ep.vt || ep.out8 || epi == EPI_RESID_LN) return hipErrorInvalidValue;
     if (a_bf16) {
         if (N % 128 == 0) return launch_cfg<bf16, 128, 128>(A, W, M, N, K, epi, ep, stream);
         return launch_cfg<bf16, 128, 64>(A, W, M, N, K, epi, ep, stream);

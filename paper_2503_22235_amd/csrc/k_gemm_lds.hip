@@ -331,6 +331,152 @@ __device__ __forceinline__ void vt_epilogue(const EpiArgs &ep, const float *bias
     }
 }
 
+// Workgroup barrier ordering LDS accesses only: the vector-memory loads and
+// stores in flight (the next stage's loads) stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Epilogue of EPI_RESID_LN (LayerNorm fused into the residual update, WM3
+// Sec. 2.1: a block's second LayerNorm reads the residual stream its
+// out-projection has just updated).  The tile spans all N features
+// of its rows.  A lane holds features ncol + 16 j + 4 g .. +3 of token
+// row0w + 16 i + r16 (tile j, row tile i): the residual update of
+// EPI_RESID, kept in acc, then the row statistics, summed in the lane (the
+// tiles in order, each tile's 4 values pairwise), over the 4 lanes g
+// (xsum16_32) and over the WGN waves of the row block through LDS, the
+// same steps for every row, so a row's result does not depend on its
+// position in the batch.  Two passes, as the LayerNorm kernel: the mean,
+// then the mean square of the deviations.
+// On gfx9 a wait for a load also waits for the stores issued before it:
+// ln_g and ln_b are loaded before the first store and go through LDS, so
+// that the normalized rows' stores wait for nothing (the updated rows are
+// stored a pair of feature tiles at a time, as in the EPI_RESID epilogue:
+// holding them to the end spills registers).
+// `red` (LDS, 2 WGN BM + 2 N floats): row sums, then ln_g and ln_b.
+template <int TM, int TN, int WGN, int BM, bool FP8>
+__device__ __forceinline__ void resid_ln_epilogue(const EpiArgs &ep, int M, int N, int mt, int row0w, int wn, int ncol,
+                                                  int g, int r16, int tid, int nth, f32x4 (&acc)[TN][TM], float *red) {
+    const float dq = FP8 ? ep.a_dequant * ep.w_dequant : 1.0f;
+    // this thread's share of ln_g and ln_b (N <= 2 nth)
+    float lg[2], lb[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int c = tid + u * nth;
+        lg[u] = c < N ? ep.ln_g[c] : 0.f;
+        lb[u] = c < N ? ep.ln_b[c] : 0.f;
+    }
+    float *xr[TM];
+    float s[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int m = min(mt + row0w + 16 * i + r16, M - 1);
+        xr[i] = state_row(ep.resid, ep.resid_ptrs, (unsigned)ep.T, ep.dT, (unsigned)(m + ep.row0), N);
+        s[i] = 0.f;
+    }
+    // residual update, a pair of feature tiles at a time
+#pragma unroll
+    for (int j = 0; j < TN; j += 2) {
+        const int n = ncol + 16 * j + 4 * g;
+        const float4 b0 = *(const float4 *)(ep.bias + n), b1 = *(const float4 *)(ep.bias + n + 16);
+        float4 rz[TM][2];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            rz[i][0] = *(const float4 *)(xr[i] + n);
+            rz[i][1] = *(const float4 *)(xr[i] + n + 16);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 b = h ? b1 : b0, r = rz[i][h];
+                f32x4 &a = acc[j + h][i];
+                // explicit FMAs, as in epilogue4
+                a[0] = r.x + fmaf(a[0], dq, b.x);
+                a[1] = r.y + fmaf(a[1], dq, b.y);
+                a[2] = r.z + fmaf(a[2], dq, b.z);
+                a[3] = r.w + fmaf(a[3], dq, b.w);
+                if (mt + row0w + 16 * i + r16 < M) *(float4 *)(xr[i] + n + 16 * h) = make_float4(a[0], a[1], a[2], a[3]);
+                s[i] += (a[0] + a[1]) + (a[2] + a[3]);
+            }
+        }
+    }
+    // row sums across the lanes g and the waves: red[w][row], then
+    // red[WGN + w][row]; ln_g and ln_b at red + 2 WGN BM
+    const float invN = 1.0f / (float)N;
+    float *const lgb = red + 2 * WGN * BM;
+    float mean[TM], rstd[TM];
+    lds_barrier();    // every wave is done with the stage slot that `red` lies in
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int c = tid + u * nth;
+        if (c < N) {
+            lgb[c] = lg[u];
+            lgb[N + c] = lb[u];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        s[i] = xsum16_32(s[i]);
+        if (g == 0) red[wn * BM + row0w + 16 * i + r16] = s[i];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        float t = red[row0w + 16 * i + r16];
+#pragma unroll
+        for (int w = 1; w < WGN; ++w) t += red[w * BM + row0w + 16 * i + r16];
+        mean[i] = t * invN;
+        float q = 0.f;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float d = acc[j][i][c] - mean[i];
+                q = fmaf(d, d, q);
+            }
+        q = xsum16_32(q);
+        if (g == 0) red[(WGN + wn) * BM + row0w + 16 * i + r16] = q;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        float t = red[WGN * BM + row0w + 16 * i + r16];
+#pragma unroll
+        for (int w = 1; w < WGN; ++w) t += red[(WGN + w) * BM + row0w + 16 * i + r16];
+        rstd[i] = 1.0f / sqrtf(t * invN + ep.ln_eps);
+    }
+    // normalized rows: bf16, or e4m3 codes at the static scale *ln_amax / 448
+    const float inv = FP8 ? (*ep.ln_amax > 0.f ? 448.0f / *ep.ln_amax : 1.0f) : 1.0f;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int n = ncol + 16 * j + 4 * g;
+        const float4 gm = *(const float4 *)(lgb + n), bt = *(const float4 *)(lgb + N + n);
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int m = mt + row0w + 16 * i + r16;
+            if (m >= M) continue;
+            const f32x4 a = acc[j][i];
+            // explicit FMAs, as in the LayerNorm kernel
+            const float y0 = fmaf((a[0] - mean[i]) * rstd[i], gm.x, bt.x) * inv;
+            const float y1 = fmaf((a[1] - mean[i]) * rstd[i], gm.y, bt.y) * inv;
+            const float y2 = fmaf((a[2] - mean[i]) * rstd[i], gm.z, bt.z) * inv;
+            const float y3 = fmaf((a[3] - mean[i]) * rstd[i], gm.w, bt.w) * inv;
+            const size_t o = (size_t)(m + ep.row0) * N + n;
+            if constexpr (FP8) {
+                *(unsigned *)((unsigned char *)ep.ln_out + o) = e4m3x4(y0, y1, y2, y3);
+            } else {
+                uint2 u;
+                u.x = pack_bf16x2(y0, y1);
+                u.y = pack_bf16x2(y2, y3);
+                *(uint2 *)((bf16 *)ep.ln_out + o) = u;
+            }
+        }
+    }
+}
+
 // FP8: operands are e4m3 bytes (128 k-values per 128-byte stage, MFMA
 // 16x16x128 f8f6f4, one k-step per stage); the epilogue dequantizes per row.
 // WGM x WGN waves tile the BM x BN output; OCC workgroups share a CU.
@@ -416,7 +562,7 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
                                                      vob[i], wsoff, 0, 0);
     };
 
-    constexpr bool ZSTART = !FP8 && EPI != EPI_QKV_ROPE;
+    constexpr bool ZSTART = !FP8 && EPI != EPI_QKV_ROPE && EPI != EPI_RESID_LN;
 
     // lane-constant fragment offsets inside a stage (swizzle depends on r16
     // only): bf16 k-step ks reads 16 bytes at k = 32ks + 8g; fp8 k-step ks
@@ -474,13 +620,28 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
             const unsigned char *sbA = aring + (st % D) * ABYTES, *sbW = wring + (st % D) * WBYTES;
             // ZSTART: a tile's first k-step starts its accumulators from an
             // inline zero operand instead of registers cleared in the previous
-            // epilogue (not for the FP8 and rotary variants, whose extra
-            // registers would spill with a second copy of the stage code)
+            // epilogue (not for the FP8, rotary and LayerNorm variants, whose
+            // extra registers would spill with a second copy of the stage code)
             if (ZSTART && kt == 0) mma_stage<ZSTART, FP8, TM, TN, KSTEPS, BKB, SWAP>(sbA, sbW, aoff, woff, acc);
             else mma_stage<false, FP8, TM, TN, KSTEPS, BKB, SWAP>(sbA, sbW, aoff, woff, acc);
         }
         const int n0 = (rw ? tn0 : tn0 + t) * BN;
         const int mt = rw ? m0 + t * BM : m0;    // first row of this tile
+        if constexpr (EPI == EPI_RESID_LN) {
+            // the launcher checks N == BN; the partial sums go to the
+            // activation slot of the tile's last stage, which no load is
+            // filling (the next tile's first stage went to the other slot)
+            static_assert((2 * WGN * BM + 2 * BN) * 4 <= ABYTES && BN <= 2 * NW * 64, "row sums and ln_g, ln_b fit a stage slot");
+            resid_ln_epilogue<TM, TN, WGN, BM, FP8>(ep, M, N, mt, wm * WM, wn, wn * WN, g, r16, tid, NW * 64, acc,
+                                                    (float *)(aring + (((t + 1) * nk - 1) % D) * ABYTES));
+            if constexpr (!ZSTART) {
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) acc[j][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+            continue;
+        }
         if constexpr (SWAP) {
             vt_epilogue<TM, TN, FP8>(ep, ep.bias + 2 * ep.C, M, mt + wm * WM, n0 - 2 * ep.C + wn * WN, acc, g, r16);
             if constexpr (!ZSTART) {
@@ -628,25 +789,33 @@ __global__ __launch_bounds__(64 * WGM * WGN, OCC) void gemm_lds_kernel(const voi
 // (measured); other N of 1536 or more take 2, smaller N take 1.
 inline int wide_tpw(int N) { return N == 1536 ? 3 : (N == 2048 ? 4 : (N >= 1536 ? 2 : 1)); }
 
-template <int BM, int BN, int BKB, int D, int WGM, int WGN, int OCC, bool FP8>
+// RLN: the instantiation for EPI_RESID_LN alone (its tile spans N), which
+// takes no other epilogue.
+template <int BM, int BN, int BKB, int D, int WGM, int WGN, int OCC, bool FP8, bool RLN = false>
 hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind epi, const EpiArgs &ep,
                       hipStream_t stream, int tpw_default = 1, int rw_default = 0) {
     constexpr size_t lds = (size_t)D * (BM + BN) * BKB;
     static_assert(lds * OCC <= 160 * 1024, "LDS per CU");
     constexpr int NTH = 64 * WGM * WGN;
+    if (RLN != (epi == EPI_RESID_LN) || (RLN && N != BN)) return hipErrorInvalidValue;
     // LDS limit of the variants, set once per process (a local static's
     // initialisation is thread-safe; the server thread launches too)
     static const hipError_t attr_err = [] {
-        const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_QKV, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_GELU, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_RESID, FP8>,
-                              (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_STORE, FP8>};
-        for (const void *f : fns) {
-            const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
+        if constexpr (RLN) {
+            return hipFuncSetAttribute((const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_RESID_LN, FP8>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        } else {
+            const void *fns[5] = {(const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_QKV, FP8>,
+                                  (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_QKV_ROPE, FP8>,
+                                  (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_GELU, FP8>,
+                                  (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_RESID, FP8>,
+                                  (const void *)gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_STORE, FP8>};
+            for (const void *f : fns) {
+                const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
         }
-        return hipSuccess;
     }();
     if (attr_err != hipSuccess) return attr_err;
     const int ntn = N / BN;
@@ -677,7 +846,9 @@ hipError_t launch_cfg(const void *A, const void *W, int M, int N, int K, EpiKind
         const int tpw = std::max(1, std::min(tpw_req, rw ? ntm : ntn));
         const int total = rw ? ((ntm + tpw - 1) / tpw) * ntn : ((ntn + tpw - 1) / tpw) * ntm;
         const int grid = ((total + 7) >> 3) << 3;
-        switch (epi) {
+        if constexpr (RLN) {
+            gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_RESID_LN, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
+        } else switch (epi) {
         case EPI_QKV:
             gemm_lds_kernel<BM, BN, BKB, D, WGM, WGN, OCC, EPI_QKV, FP8><<<grid, NTH, lds, stream>>>(Ac, W, Mc, N, K, e, tpw, rw);
             break;
@@ -733,6 +904,12 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
         const char *v = getenv("WM_GEMM_CFG");
         return v ? atoi(v) : -1;
     }();
+    // EPI_RESID_LN: 128 x 512 tiles (8 waves, 2 x 4, the same 64 x 128
+    // wave tile), two stages of 80 KB, two row blocks per workgroup
+    if (epi == EPI_RESID_LN) {
+        if (!gemm_resid_ln_applies(N) || ep.out8 || ep.out_amax || ep.perm || !ep.ln_g || !ep.ln_b || !ep.ln_out) return hipErrorInvalidValue;
+        return launch_cfg<128, 512, 128, 2, 2, 4, 1, false, true>(A, W, M, N, K, epi, ep, stream, 2, 1);
+    }
     // (a QKV feature tile must not straddle two of Q, K and V: BN divides C)
     const bool n256 = N % 256 == 0 && (!epi_qkv(epi) || ep.C % 256 == 0);
     switch (cfg) {
@@ -768,6 +945,14 @@ hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, Ep
         const char *v = getenv("WM_GEMM_CFG");
         return v ? atoi(v) : -1;
     }();
+    if (epi == EPI_RESID_LN) {
+        // as in launch_gemm_lds; one dequantization scale for all rows, and
+        // the LayerNorm output as e4m3 codes (out8) at a given scale
+        if (!gemm_resid_ln_applies(N) || ep.a_amax || !ep.out8 || !ep.ln_amax || ep.out_amax || ep.perm || !ep.ln_g ||
+            !ep.ln_b || !ep.ln_out)
+            return hipErrorInvalidValue;
+        return launch_cfg<128, 512, 128, 2, 2, 4, 1, true, true>(A, W, M, N, K, epi, ep, stream, 2, 1);
+    }
     if (epi_qkv(epi) && ep.vt) {
         if (ep.a_amax) return hipErrorInvalidValue;   // V tiles dequantize with the one scale a_dequant
         // a workgroup's feature tiles must be all V or none (as in launch_gemm_lds)

@@ -110,15 +110,6 @@ __global__ void nat_bias_prep(NatArgs p) {
     p.tbl_ws[e] = v;
 }
 
-// Sum over the 4 lanes l, l^16, l^32, l^48 (the lanes that share a query);
-// every one of them gets the same bits (same operand order).
-__device__ __forceinline__ float xsum16_32(float v) {
-    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
-    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
-    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
-}
-
 typedef __attribute__((address_space(3))) void lds_void;
 
 // bf16 tile kernel for token-major v.  The V halo sits in LDS as slabs of

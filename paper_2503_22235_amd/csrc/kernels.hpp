@@ -30,7 +30,9 @@ enum EpiKind : int {
     EPI_GELU = 1,   // gelu(+bias) -> out [M][N]
     EPI_RESID = 2,  // resid[m][n] += acc + bias (float32 in place)
     EPI_STORE = 3,  // +bias -> out [M][N]
-    EPI_QKV_ROPE = 4  // EPI_QKV with q and k rotated (EpiArgs.rope)
+    EPI_QKV_ROPE = 4, // EPI_QKV with q and k rotated (EpiArgs.rope)
+    EPI_RESID_LN = 5  // EPI_RESID, then the LayerNorm of each updated row
+                      // (EpiArgs.ln_*); LDS GEMMs with N = 512 only
 };
 constexpr bool epi_qkv(int e) { return e == EPI_QKV || e == EPI_QKV_ROPE; }
 // Division of n < 2^31 by a fixed d >= 1 as a multiply-high and a shift
@@ -101,6 +103,13 @@ struct EpiArgs {
     // the GELU output as [M][N] bytes.
     int out8;
     float out_mul[3];
+    // EPI_RESID_LN: every updated row x' of the target (all N features) is
+    // also written layer-normalized to ln_out [M][N]:
+    // (x' - mean) / sqrt(var + ln_eps) * ln_g + ln_b, as bf16, or, with out8
+    // set, as e4m3 codes of that value times 448 / *ln_amax.
+    const float *ln_g, *ln_b, *ln_amax;
+    void *ln_out;
+    float ln_eps;
 };
 // Rotary position embedding of cnt consecutive channels e.. (e even) of a
 // q or k head row at global row mg (token mg mod T): channel pair p =
@@ -140,6 +149,9 @@ hipError_t launch_gemm_lds(const void *A, const void *W, int M, int N, int K, Ep
 // e4m3 operands (A [M][K], W [N][K] bytes); needs N % 128 == 0, K % 128 == 0.
 hipError_t launch_gemm_fp8(const void *A, const void *W, int M, int N, int K, EpiKind epi,
                            const EpiArgs &ep, hipStream_t stream);
+// Whether the LDS GEMMs take EPI_RESID_LN for this output width (a
+// workgroup's tile must span every feature of its rows).
+inline bool gemm_resid_ln_applies(int N) { return N == 512; }
 
 // --- FP8 quantization (OCP e4m3; per-state scale amax / 448) --------------
 // amax slots live in AMAX_SHARDS copies AMAX_STRIDE apart; producers write

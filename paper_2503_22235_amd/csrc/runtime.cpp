@@ -83,8 +83,13 @@ int prof_end(wm_ctx *ctx, hipStream_t s) {
 static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, float *const *xs,
                          hipStream_t s);
 
+bool block_fuses_ln(const wm_processor *p) {
+    return (p->prec == WM_BF16 || p->prec == WM_FP8_E4M3) && gemm_resid_ln_applies(p->g.C);
+}
+
 int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, float *const *xs, hipStream_t s) {
     if (p->prec == WM_FP8_E4M3) return run_block_fp8(ctx, p, block, B, x, xs, s);
+    const bool fuse = block_fuses_ln(p);
     const wm_grid &g = p->g;
     const BlockWeights &w = p->blk[block];
     const long T = (long)g.Z * g.Y * g.X;
@@ -181,8 +186,18 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, fl
     er.resid_ptrs = xs;
     er.T = T;
     er.dT = udiv_make((unsigned)T);
-    WM_TIMED(PK_PROJ, launch_gemm(act, w.w_o, M, C, C, bf, EPI_RESID, er, s), "proj")
-    WM_TIMED(PK_LN2, launch_layernorm(xr, w.ln2_g, w.ln2_b, act, bf, M, C, 1e-5f, s), "LN2")
+    if (fuse) {
+        // LN2 of each updated row into act, over the projection's own input
+        // rows (a workgroup has read all of its rows of A by then)
+        er.ln_g = w.ln2_g;
+        er.ln_b = w.ln2_b;
+        er.ln_out = act;
+        er.ln_eps = 1e-5f;
+        WM_TIMED(PK_PROJ, launch_gemm(act, w.w_o, M, C, C, bf, EPI_RESID_LN, er, s), "proj + LN2")
+    } else {
+        WM_TIMED(PK_PROJ, launch_gemm(act, w.w_o, M, C, C, bf, EPI_RESID, er, s), "proj")
+        WM_TIMED(PK_LN2, launch_layernorm(xr, w.ln2_g, w.ln2_b, act, bf, M, C, 1e-5f, s), "LN2")
+    }
     EpiArgs eg{};
     eg.bias = w.b_1;
     eg.out = big;
@@ -209,6 +224,7 @@ int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, fl
 // stay float32.
 static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, float *const *xs,
                          hipStream_t s) {
+    const bool fuse = block_fuses_ln(p);
     const wm_grid &g = p->g;
     const BlockWeights &w = p->blk[block];
     const long T = (long)g.Z * g.Y * g.X;
@@ -285,8 +301,19 @@ static int run_block_fp8(wm_ctx *ctx, const wm_processor *p, int block, int B, f
     er.a_dequant = w.qkv_amax_h[2] / 448.0f;   // o is coded at v's scale
     er.w_dequant = w.dq_o;
     er.T = T;
-    WM_TIMED(PK_PROJ, launch_gemm_fp8(o8, w.w_o, M, C, C, EPI_RESID, er, s), "proj")
-    WM_TIMED(PK_LN2, launch_layernorm_fp8_static(xr, w.ln2_g, w.ln2_b, M, C, 1e-5f, w.ln2_amax, act8, s), "LN2")
+    if (fuse) {
+        // LN2 codes of each updated row into act8 (static scale ln2_amax)
+        er.ln_g = w.ln2_g;
+        er.ln_b = w.ln2_b;
+        er.ln_amax = w.ln2_amax;
+        er.ln_out = act8;
+        er.ln_eps = 1e-5f;
+        er.out8 = 1;
+        WM_TIMED(PK_PROJ, launch_gemm_fp8(o8, w.w_o, M, C, C, EPI_RESID_LN, er, s), "proj + LN2")
+    } else {
+        WM_TIMED(PK_PROJ, launch_gemm_fp8(o8, w.w_o, M, C, C, EPI_RESID, er, s), "proj")
+        WM_TIMED(PK_LN2, launch_layernorm_fp8_static(xr, w.ln2_g, w.ln2_b, M, C, 1e-5f, w.ln2_amax, act8, s), "LN2")
+    }
     EpiArgs eg{};
     eg.bias = w.b_1;
     eg.out = h8;

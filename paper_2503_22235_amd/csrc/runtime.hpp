@@ -106,6 +106,9 @@ int prof_end(wm_ctx *ctx, hipStream_t s);
 // x: the float32 residual stream [B*T][C] in one buffer, or (xs set, x
 // unused) B states in separate buffers whose pointers are in the device
 // array xs.
+// Blocks whose LN2 runs in the epilogue of the out-projection (bf16 and
+// FP8 at C = 512).
+bool block_fuses_ln(const wm_processor *p);
 int run_block(wm_ctx *ctx, const wm_processor *p, int block, int B, float *x, float *const *xs, hipStream_t s);
 int run_step(wm_ctx *ctx, const wm_processor *p, int B, float *x, float *const *xs, hipStream_t s);
 // Host OCP e4m3 encoding, round to nearest even, saturating at +-448.
