@@ -32,16 +32,24 @@ PEAK_EXP_GPS = 256 * 4 * 16 / 4 * 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_8x90x180.json")
 
 
+def fused_ln2(g):
+    """Whether a bf16 (or FP8) block runs LN2 in the epilogue of its
+    out-projection (at C = 512, where one workgroup's tile spans a row)."""
+    return g.C == 512
+
+
 def block_kernel_work(g, B=1, mlp=4):
     """Algorithmic FLOPs and HBM bytes per launch of each block kernel (bf16).
 
     Bytes count every operand read once and every result written once (bf16
-    activations, float32 residual stream, weights once)."""
+    activations, float32 residual stream, weights once).  With LN2 fused,
+    "proj" also counts the LayerNorm's FLOPs and its bf16 output; the rows it
+    normalizes are already in registers."""
     T = g.Z * g.Y * g.X * B
     C, F, H = g.C, g.C * mlp, g.heads
     kvol = g.Kz * g.Ky * g.Kx
     a = 2
-    return {
+    w = {
         "ln1": (8.0 * T * C, T * C * 4 + T * C * a),
         "qkv": (2.0 * T * C * 3 * C, T * C * a + 3 * C * C * a + T * 3 * C * a),
         "nat": (4.0 * T * H * kvol * 32, 3 * T * C * a + T * C * a),
@@ -50,6 +58,11 @@ def block_kernel_work(g, B=1, mlp=4):
         "mlp1": (2.0 * T * C * F, T * C * a + C * F * a + T * F * a),
         "mlp2": (2.0 * T * F * C, T * F * a + F * C * a + 2 * T * C * 4),
     }
+    if fused_ln2(g):
+        lf, _ = w.pop("ln2")
+        pf, pb = w["proj"]
+        w["proj"] = (pf + lf, pb + T * C * a)
+    return w
 
 
 def roofline(g, kind, avg_us):
@@ -236,7 +249,9 @@ def host_cpu():
     return {"nproc": len(os.sched_getaffinity(0)), "online": os.cpu_count(), "model": model}
 
 
-KIND_ORDER = ("ln1", "qkv", "nat", "proj", "ln2", "mlp1", "mlp2")
+def kind_order(g):
+    """The block's kernel launches in order (LN2 absent when it is fused)."""
+    return tuple(k for k in ("ln1", "qkv", "nat", "proj", "ln2", "mlp1", "mlp2") if k != "ln2" or not fused_ln2(g))
 
 
 def _counter_rows(d, counter):
@@ -254,12 +269,12 @@ def _counter_rows(d, counter):
     return rows
 
 
-def _per_kind(rows):
+def _per_kind(rows, order):
     """Sum a counter per block-kernel launch, launches identified by their
-    order inside a block: LN, GEMM, attention, GEMM, LN, GEMM, GEMM.  A bias
-    table preparation counts with the attention launch that follows it; one
-    followed by anything else (a processor's tables, prepared at creation) is
-    not part of a block."""
+    order inside a block (`order`: LN, GEMM, attention, GEMM, [LN,] GEMM,
+    GEMM).  A bias table preparation counts with the attention launch that
+    follows it; one followed by anything else (a processor's tables,
+    prepared at creation) is not part of a block."""
     want = {"ln1": "ln", "qkv": "gemm", "nat": "nat", "proj": "gemm", "ln2": "ln", "mlp1": "gemm", "mlp2": "gemm"}
     launches = []
     prep = None
@@ -274,11 +289,11 @@ def _per_kind(rows):
             raise SystemExit(f"unexpected library kernel {name}")
         launches.append([t, v + (prep if t == "nat" and prep is not None else 0.0)])
         prep = None
-    if len(launches) % 7:
+    if len(launches) % len(order):
         raise SystemExit(f"{len(launches)} launches is not a whole number of blocks")
-    acc = {k: [] for k in KIND_ORDER}
+    acc = {k: [] for k in order}
     for i, (t, v) in enumerate(launches):
-        k = KIND_ORDER[i % 7]
+        k = order[i % len(order)]
         if want[k] != t:
             raise SystemExit(f"launch {i}: expected {want[k]}, found {t}")
         acc[k].append(v)
@@ -297,10 +312,11 @@ def traffic_from(fetch_dir, write_dir, copy_mib):
     if not cf or not cw:
         raise SystemExit("copy probe dispatches not found")
     ff, fw = (sum(cf) / len(cf)) / known_kib, (sum(cw) / len(cw)) / known_kib
-    fk, wk = _per_kind(f_rows), _per_kind(w_rows)
+    order = kind_order(g_)
+    fk, wk = _per_kind(f_rows, order), _per_kind(w_rows, order)
     work = block_kernel_work(g_)
     kern = {}
-    for k in KIND_ORDER:
+    for k in order:
         rb, wb = fk[k] * 1024.0 / ff, wk[k] * 1024.0 / fw
         kern[k] = {"fetch_bytes": round(rb), "write_bytes": round(wb), "hbm_bytes_per_launch": round(rb + wb),
                    "algorithmic_bytes": work[k][1], "ratio": round((rb + wb) / work[k][1], 3)}

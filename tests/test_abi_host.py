@@ -191,5 +191,14 @@ def test_counter_attribution_per_block_kernel():
     cached = [b for b in block if "bias_prep" not in b[0]]
     rows = [(ns + "nat_bias_prep", 100.0)] * 3 + [("at::neg_kernel", 9.0)] + block + cached
     rows = [(i, n, v) for i, (n, v) in enumerate(rows)]
-    got = bench._per_kind(rows)
+    import wm_synth as S
+    got = bench._per_kind(rows, bench.kind_order(S.CFG1))
     assert got == {"ln1": 1.0, "qkv": 2.0, "nat": 3.25, "proj": 4.0, "ln2": 5.0, "mlp1": 6.0, "mlp2": 7.0}
+    # C = 512: LN2 runs inside the out-projection, six launches per block
+    fused = [b for b in block if b[1] != 5.0]
+    rows = [(i, n, v) for i, (n, v) in enumerate(fused + [b for b in fused if "bias_prep" not in b[0]])]
+    assert bench.kind_order(S.CFG2) == ("ln1", "qkv", "nat", "proj", "mlp1", "mlp2")
+    got = bench._per_kind(rows, bench.kind_order(S.CFG2))
+    assert got == {"ln1": 1.0, "qkv": 2.0, "nat": 3.25, "proj": 4.0, "mlp1": 6.0, "mlp2": 7.0}
+    with pytest.raises(SystemExit):     # seven launches per block are not the fused order
+        bench._per_kind([(i, n, v) for i, (n, v) in enumerate(block)], bench.kind_order(S.CFG2))
