@@ -40,6 +40,14 @@ __device__ __forceinline__ float bf2f(bf16 b) {
     return bf_bits2f(__builtin_bit_cast(unsigned short, b));
 }
 
+// s_waitcnt with vmcnt <= n and no wait on the other counters (gfx9 encoding:
+// vmcnt bits [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]).
+template <int n>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(n >= 0 && n < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 // Sum over the 4 lanes l, l^16, l^32, l^48 (in the MFMA layouts, the lanes
 // that hold the same token or query); every one of them gets the same bits
 // (same operand order).

@@ -163,14 +163,6 @@ __device__ __forceinline__ float epilogue8(const EpiArgs &ep, int N, long mg, in
     return m;
 }
 
-// s_waitcnt with vmcnt <= n and no wait on the other counters (gfx9 encoding:
-// vmcnt bits [3:0] and [15:14], expcnt [6:4], lgkmcnt [11:8]).
-template <int n>
-__device__ __forceinline__ void wait_vmcnt() {
-    static_assert(n >= 0 && n < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
 // Wait until at most min(later, D - 2) stages of PER load instructions each
 // are still in flight (later: stages issued after the one waited for).
 template <int PER, int D>

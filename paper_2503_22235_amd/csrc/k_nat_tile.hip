@@ -784,7 +784,13 @@ __global__ void nat_bias_prep_fp8(NatArgs p) {
 // q8, in e4m3; the output in bf16 or, with o8, as e4m3 codes at v's scale.
 // A level is 10 lat rows of K (16 tokens x 32 bytes, the 16-byte halves of
 // token c in row R swapped when bit 1 of R is set, against bank conflicts)
-// and 10 of V (512 bytes), 10 KB; two slots alternate.  Reference: each
+// and 10 of V (512 bytes), 10 KB; three slots rotate, so the loads of two
+// levels are in flight while one is computed (a wave waits for its own part
+// of a level with a vmcnt that leaves the next level's loads in flight, then
+// a bare barrier).  35 KB of LDS and 128 VGPRs: four workgroups share a CU
+// (the level walk is a loop, not unrolled, to stay within the registers;
+// measured 262 -> 239 us per state at 8x90x180 with B = 4 against two slots
+// and three workgroups per CU).  Reference: each
 // query's own score; the weights are exp2(c (s - m)), and if a score
 // exceeds m by more than TAU / c (a weight above 2^TAU, outside what the
 // e4m3 weights hold with the static scale) the workgroup finds the exact
@@ -805,7 +811,7 @@ __device__ __forceinline__ float e4m3_dot4(unsigned a, unsigned b, float s) {
 }
 
 template <int KZ, int KY, int KX>
-__global__ __launch_bounds__(256, 3) void nat_ring_fp8_kernel(NatArgs p, TileDiv dm) {
+__global__ __launch_bounds__(256, 4) void nat_ring_fp8_kernel(NatArgs p, TileDiv dm) {
     constexpr int RX = (KX - 1) / 2;
     constexpr int BY = 2 * KY - 1;
     constexpr int TBL = (2 * KZ - 1) * BY * XT;
@@ -888,6 +894,7 @@ __global__ __launch_bounds__(256, 3) void nat_ring_fp8_kernel(NatArgs p, TileDiv
         }
     };
     stage(0, 0);
+    if (zn > 1) stage(1, 1);
     {
         const uint4 *src = (const uint4 *)(p.tbl_ws + ((size_t)b * p.H + h) * TBLP);
         for (int e = tid; e < TBLP / 4; e += 256) ((uint4 *)tbl)[e] = src[e];
@@ -946,7 +953,7 @@ __global__ __launch_bounds__(256, 3) void nat_ring_fp8_kernel(NatArgs p, TileDiv
         const uint2 ks = *(const uint2 *)(k8 + qtok[G] * p.ts + 8 * g);
         mref[G] = xsum16_32(e4m3_dot4(q8.y, ks.y, e4m3_dot4(q8.x, ks.x, 0.f)));                     // the query's own score, raw units (bias below)
     }
-    __syncthreads();     // bias table and level 0 in LDS
+    __syncthreads();     // bias table and levels 0 and 1 in LDS
     {
         const float tcenter = tbl[((KZ - 1) * BY + KY - 1) * XT + 1 + RX];
 #pragma unroll
@@ -963,13 +970,24 @@ __global__ __launch_bounds__(256, 3) void nat_ring_fp8_kernel(NatArgs p, TileDiv
             oacc[G][0] = oacc[G][1] = lacc[G] = f32x4{0.f, 0.f, 0.f, 0.f};
             nmc[G] = -c * mref[G];
         }
-        for (int hz0 = 0; hz0 < zn; hz0 += 2)
-#pragma unroll
-        for (int lv = 0; lv < 2; ++lv) {
-            const int hz = hz0 + lv;
-            if (hz >= zn) break;                  // uniform
-            if (hz > 0) __syncthreads();          // level hz landed; level hz - 1 is done with
-            if (hz + 1 < zn) stage(hz + 1, lv ^ 1);
+        for (int hz = 0, lv = 0; hz < zn; ++hz, lv = lv == 2 ? 0 : lv + 1) {
+            if (hz > 0) {
+                // this wave's loads of level hz have landed once at most those
+                // of level hz + 1 (3 instructions for waves 0 and 1, 2 for
+                // waves 2 and 3, issued later) are outstanding; the barrier
+                // then makes every wave's part visible and frees the slot of
+                // level hz - 1 (levels 0 and 1 were waited for before the walk)
+                if (hz > 1) {
+                    if (hz + 1 < zn) {
+                        if (wave < 2) wait_vmcnt<3>();
+                        else wait_vmcnt<2>();
+                    } else {
+                        wait_vmcnt<0>();
+                    }
+                }
+                __builtin_amdgcn_s_barrier();
+            }
+            if (hz + 2 < zn) stage(hz + 2, lv == 0 ? 2 : lv - 1);
             const unsigned char *sl = ring + lv * RING8_SLOT;
             const bool okz = (unsigned)(hz - wz) < (unsigned)KZ;
             const int tbh = tb_lane + hz * BY * XT;
@@ -1064,6 +1082,7 @@ __global__ __launch_bounds__(256, 3) void nat_ring_fp8_kernel(NatArgs p, TileDiv
             for (int G = 0; G < 2; ++G) mref[G] = xmax16_32(me[G]);
         }
         stage(0, 0);
+        if (zn > 1) stage(1, 1);
         __syncthreads();
     }
 
@@ -1573,7 +1592,7 @@ hipError_t launch_tile_fp8(const NatArgs &a, hipStream_t stream) {
 
 size_t ring8_lds(int Kz, int Ky) {
     const int tblp = (((2 * Kz - 1) * (2 * Ky - 1) * XT + NEG_RUN + 3) & ~3);
-    return (size_t)tblp * 4 + 2 * (size_t)RING8_SLOT;
+    return (size_t)tblp * 4 + 3 * (size_t)RING8_SLOT;
 }
 
 template <int KZ, int KY, int KX>
