@@ -202,3 +202,24 @@ def test_counter_attribution_per_block_kernel():
     assert got == {"ln1": 1.0, "qkv": 2.0, "nat": 3.25, "proj": 4.0, "mlp1": 6.0, "mlp2": 7.0}
     with pytest.raises(SystemExit):     # seven launches per block are not the fused order
         bench._per_kind([(i, n, v) for i, (n, v) in enumerate(block)], bench.kind_order(S.CFG2))
+
+
+def test_block_kernel_work_with_fused_ln2():
+    """At C = 512 LN2 runs in the out-projection's epilogue: the algorithmic
+    work of "proj" adds LN2's FLOPs and its bf16 output (the rows it reads are
+    the ones the projection just wrote), and there is no "ln2" launch.  Other
+    widths keep the separate LayerNorm with the same figures as LN1."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    import wm_synth as S
+    g = S.CFG2
+    T, C = g.Z * g.Y * g.X, g.C
+    w = bench.block_kernel_work(g)
+    assert "ln2" not in w and set(w) == set(bench.kind_order(g))
+    assert w["proj"] == (2.0 * T * C * C + 8.0 * T * C, T * C * 2 + C * C * 2 + 2 * T * C * 4 + T * C * 2)
+    g1 = S.CFG1
+    T1, C1 = g1.Z * g1.Y * g1.X, g1.C
+    w1 = bench.block_kernel_work(g1)
+    assert w1["ln2"] == w1["ln1"] == (8.0 * T1 * C1, T1 * C1 * 6)
+    assert w1["proj"] == (2.0 * T1 * C1 * C1, T1 * C1 * 2 + C1 * C1 * 2 + 2 * T1 * C1 * 4)
